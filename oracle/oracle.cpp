@@ -32,7 +32,6 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
-#include <set>
 #include <vector>
 
 namespace {
@@ -75,30 +74,33 @@ int oracle_reindex(const uint32_t* vtx, int64_t num_vtx, int32_t words,
     }
   }
 
+  // One entry per distinct value, keyed (and therefore iterated) in key order.
+  struct Group {
+    int32_t rep;     // smallest original id holding this value
+    bool used;       // referenced through any of its copies
+    int32_t new_id;  // position among used values, -1 if unused
+  };
+  std::map<Key, Group> groups;
+
   // 1. representative: first occurrence in original-id order.
-  std::map<Key, int32_t> rep;
-  for (int64_t i = 0; i < num_vtx; ++i) rep.emplace(key_of(vtx, i, words), (int32_t)i);
+  for (int64_t i = 0; i < num_vtx; ++i) groups.emplace(key_of(vtx, i, words), Group{(int32_t)i, false, -1});
 
   // 2. a value is used iff any copy of it is referenced.
-  std::set<Key> used;
-  for (int64_t k = 0; k < num_idx; ++k) used.insert(key_of(vtx, idx[k], words));
+  for (int64_t k = 0; k < num_idx; ++k) groups.at(key_of(vtx, idx[k], words)).used = true;
 
   // 3. used values in ascending key order get consecutive new ids.
-  std::map<Key, int32_t> new_id;
   int64_t u = 0;
-  for (const auto& kv : rep) {
-    if (used.count(kv.first) == 0) continue;
-    new_id[kv.first] = (int32_t)u;
-    std::memcpy(out_vtx + u * words, vtx + (int64_t)kv.second * words, sizeof(uint32_t) * words);
-    new2old[u] = kv.second;
+  for (auto& kv : groups) {
+    Group& g = kv.second;
+    if (!g.used) continue;
+    g.new_id = (int32_t)u;
+    std::memcpy(out_vtx + u * words, vtx + (int64_t)g.rep * words, sizeof(uint32_t) * words);
+    new2old[u] = g.rep;
     ++u;
   }
 
   // 4. old -> new for every original vertex (-1: its value is not used).
-  for (int64_t i = 0; i < num_vtx; ++i) {
-    auto it = new_id.find(key_of(vtx, i, words));
-    old2new[i] = (it == new_id.end()) ? -1 : it->second;
-  }
+  for (int64_t i = 0; i < num_vtx; ++i) old2new[i] = groups.at(key_of(vtx, i, words)).new_id;
 
   // 5. remap every index entry.
   for (int64_t k = 0; k < num_idx; ++k) out_idx[k] = old2new[idx[k]];

@@ -1,0 +1,22 @@
+"""meshrx: GPU re-indexing of indexed meshes (duplicate- and unused-vertex
+removal) for AMD MI355X, after Wald's parallel re-indexing method (sort,
+run-head flags, prefix sums, scatters, index remap).
+
+The compute lives in libmeshrx.so (hand-written HIP for gfx950, C ABI in
+include/meshrx.h); this package only marshals arguments.
+"""
+from ._lib import MeshrxError, load, tunings  # noqa: F401
+
+__all__ = ["MeshrxError", "load", "tunings", "reindex_mesh", "reindex_mesh_batched",
+           "gather_attrs", "GatherAttrs", "BatchedReindexer", "GraphedBatchedReindexer",
+           "Reindexer", "workspace_size"]
+
+
+def __getattr__(name):
+    # torch-dependent API is imported on first use
+    if name in ("reindex_mesh", "reindex_mesh_batched", "gather_attrs", "GatherAttrs",
+                "BatchedReindexer", "GraphedBatchedReindexer", "workspace_size", "Reindexed", "Reindexer",
+                "BatchReindexed"):
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

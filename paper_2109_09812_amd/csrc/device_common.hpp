@@ -1,0 +1,197 @@
+// Device-side building blocks shared by the meshrx kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrx {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (uint64_t(1) << lane_id()) - 1;  // lane 0 -> 0
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// Inclusive scan of a 32-bit value across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    uint32_t t = __shfl_up(v, off, kWave);
+    if (lane_id() >= off) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over all threads of a block (BLOCK threads, BLOCK % 64 == 0).
+// `s_wave` must hold BLOCK/64 words of LDS. Returns the exclusive prefix and
+// the block total in *total. Contains __syncthreads().
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave,
+                                                         uint32_t* total) {
+  constexpr int WAVES = BLOCK / kWave;
+  const int wave = threadIdx.x / kWave;
+  uint32_t inc = wave_inclusive_scan(v);
+  if (lane_id() == kWave - 1) s_wave[wave] = inc;
+  __syncthreads();
+  uint32_t wave_base = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    uint32_t t = s_wave[w];
+    if (w < wave) wave_base += t;
+    sum += t;
+  }
+  *total = sum;
+  __syncthreads();  // s_wave may be reused by the caller afterwards
+  return wave_base + inc - v;
+}
+
+// ---------------------------------------------------------------- look-back
+//
+// Decoupled look-back state: one 64-bit word per (tile, bin).
+//   bits  0..31  value (a count, < 2^31)
+//   bits 32..47  tag   (which launch of the call wrote it; 0 = cleared)
+//   bits 48..49  status: 1 = tile aggregate only, 2 = inclusive prefix
+// The value travels inside the same atomic word as its status, so relaxed
+// agent-scope atomics suffice: no other memory is published through it.
+
+constexpr uint64_t kLbAggregate = 1;
+constexpr uint64_t kLbInclusive = 2;
+
+__device__ __forceinline__ uint64_t lb_pack(uint64_t status, uint32_t tag, uint32_t value) {
+  return (status << 48) | (uint64_t(tag & 0xFFFFu) << 32) | uint64_t(value);
+}
+
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t flag_load(const int32_t* p) {
+  return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Upper bound on polls of one look-back word. A predecessor tile has already
+// claimed its tile id and is running, so in a correct launch it publishes
+// within microseconds; the bound only keeps a broken launch from hanging.
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// Control block kept in the (zeroed) workspace.
+struct Control {
+  int32_t abort;        // set once any wait exceeds kSpinLimit; all waits then give up
+  int32_t status;       // internal status word used when the caller passes none
+  int32_t pad[2];
+  int64_t num_groups;   // G: distinct values (per mesh, for a batch) among all vertices
+  int64_t num_used;     // U of a batch (all meshes)
+};
+
+// Exclusive prefix over tiles [0, tile) for one bin, by walking back from
+// tile-1 until an inclusive prefix is found. `stride` is the distance in
+// words between consecutive tiles' entries for this bin.
+__device__ __forceinline__ uint32_t lookback_exclusive(const uint64_t* base, int64_t tile,
+                                                       int64_t stride, uint32_t tag,
+                                                       Control* ctl, int32_t* status) {
+  uint32_t excl = 0;
+  int64_t t = tile - 1;
+  uint32_t spins = 0;
+  while (t >= 0) {
+    uint64_t v = lb_load(base + t * stride);
+    uint64_t st = v >> 48;
+    uint32_t vtag = uint32_t(v >> 32) & 0xFFFFu;
+    if (st == 0 || vtag != (tag & 0xFFFFu)) {
+      if (++spins >= kSpinLimit || flag_load(&ctl->abort)) {
+        __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicMax(status, 7 /* MRX_ERR_INTERNAL */);
+        return excl;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += uint32_t(v);
+    if (st == kLbInclusive) break;
+    --t;
+  }
+  return excl;
+}
+
+// Dynamic tile id: tiles are claimed in dispatch order, so every tile a
+// claimant waits on has already started.
+__device__ __forceinline__ uint32_t claim_tile(uint32_t* counter, uint32_t* s_slot) {
+  if (threadIdx.x == 0) *s_slot = atomicAdd(counter, 1u);
+  __syncthreads();
+  uint32_t t = *s_slot;
+  return t;
+}
+
+// ---------------------------------------------------------------- element I/O
+//
+// Sort elements are S = K + 1 uint32 words: K key words then the original
+// vertex id (bit 31 = "some index entry references this vertex").
+
+template <int S>
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ p, uint32_t (&v)[S]) {
+  if constexpr (S % 4 == 0) {
+#pragma unroll
+    for (int w = 0; w < S; w += 4) {
+      uint4 x = *reinterpret_cast<const uint4*>(p + w);
+      v[w] = x.x; v[w + 1] = x.y; v[w + 2] = x.z; v[w + 3] = x.w;
+    }
+  } else if constexpr (S % 2 == 0) {
+#pragma unroll
+    for (int w = 0; w < S; w += 2) {
+      uint2 x = *reinterpret_cast<const uint2*>(p + w);
+      v[w] = x.x; v[w + 1] = x.y;
+    }
+  } else {
+#pragma unroll
+    for (int w = 0; w < S; ++w) v[w] = p[w];
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void store_words(uint32_t* __restrict__ p, const uint32_t (&v)[S]) {
+  if constexpr (S % 4 == 0) {
+#pragma unroll
+    for (int w = 0; w < S; w += 4)
+      *reinterpret_cast<uint4*>(p + w) = make_uint4(v[w], v[w + 1], v[w + 2], v[w + 3]);
+  } else if constexpr (S % 2 == 0) {
+#pragma unroll
+    for (int w = 0; w < S; w += 2) *reinterpret_cast<uint2*>(p + w) = make_uint2(v[w], v[w + 1]);
+  } else {
+#pragma unroll
+    for (int w = 0; w < S; ++w) p[w] = v[w];
+  }
+}
+
+// Word `i` of a register array, `i` wave-uniform (a select chain, no scratch).
+template <int N>
+__device__ __forceinline__ uint32_t pick_word(const uint32_t (&v)[N], int i) {
+  uint32_t r = v[0];
+#pragma unroll
+  for (int w = 1; w < N; ++w) r = (i == w) ? v[w] : r;
+  return r;
+}
+
+// Mesh id of global vertex id `id` in a packed batch: the b with
+// off[b] <= id < off[b+1] (binary search; off has nmesh+1 entries).
+__device__ __forceinline__ uint32_t mesh_of(const int64_t* __restrict__ off, int32_t nmesh,
+                                            int64_t id) {
+  int32_t lo = 0, hi = nmesh;  // invariant: off[lo] <= id < off[hi]
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= id) lo = mid; else hi = mid;
+  }
+  return uint32_t(lo);
+}
+
+}  // namespace mrx

@@ -1,0 +1,601 @@
+// meshrx C ABI: argument validation, workspace layout and the launch
+// sequence of the re-indexing pipeline (Section 2, Steps 1-4), plus the
+// attribute gather and its backward.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/meshrx.h"
+#include "registry.hpp"
+
+namespace mrx {
+
+// Zero a 16-byte aligned byte range (the per-call control state) and the
+// caller's status word.
+__global__ void k_fill_zero(uint4* __restrict__ p, int64_t n16, int32_t* status, int64_t* count) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (status) *status = 0;
+    if (count) *count = 0;
+  }
+}
+
+// Batch epilogue: out_off[b] = number of used groups of meshes < b, read
+// from cmap at the first sorted position of mesh b (a head, since heads
+// break at mesh starts); new2old made mesh-local.
+__global__ void k_batch_offsets(const int64_t* __restrict__ vtx_off, int32_t nmesh,
+                                const uint32_t* __restrict__ sorted, int32_t S,
+                                const int32_t* __restrict__ o2g, const int32_t* __restrict__ cmap,
+                                const Control* ctl, const int64_t* __restrict__ total_used,
+                                int64_t n, int64_t* __restrict__ out_off) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nmesh) return;
+  const int64_t p = vtx_off[b];
+  int64_t r = *total_used;
+  if (b < nmesh && p < n) {
+    const uint32_t org = sorted[p * S + (S - 1)] & 0x7FFFFFFFu;
+    const int32_t g = org < n ? o2g[org] : -1;
+    if (g >= 0 && g < ctl->num_groups) {
+      const int32_t c = cmap[g];
+      r = c >= 0 ? c : ~c;
+    }
+  }
+  out_off[b] = r;
+}
+
+__global__ void k_localize_new2old(int32_t* __restrict__ new2old, const int64_t* __restrict__ total_used,
+                                   const int64_t* __restrict__ vtx_off, int32_t nmesh) {
+  const int64_t u = *total_used;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < u; j += stride) {
+    const int32_t g = new2old[j];
+    new2old[j] = g - int32_t(vtx_off[mesh_of(vtx_off, nmesh, g)]);
+  }
+}
+
+namespace {
+
+// ---------------------------------------------------------------- profiling
+struct ProfRecord {
+  const char* name;  // null: end of a call
+  hipEvent_t event;
+};
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<ProfRecord> recs;
+
+  hipEvent_t take() {
+    if (next == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[next++];
+  }
+};
+
+Profiler& profiler() {
+  static Profiler p;
+  return p;
+}
+
+// Records a timing event on the stream before a kernel launch (name != null)
+// or after the last launch of a call (name == null). Kernel i of a call runs
+// between its mark and the next one, since the stream executes in order.
+void prof_mark(const char* name, hipStream_t s) {
+  Profiler& p = profiler();
+  if (!p.on) return;
+  std::lock_guard<std::mutex> g(p.mu);
+  hipEvent_t e = p.take();
+  if (!e) return;
+  if (hipEventRecord(e, s) != hipSuccess) return;
+  p.recs.push_back(ProfRecord{name, e});
+}
+
+constexpr int64_t kMaxCount = int64_t(INT32_MAX);  // ids and counts are int32
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+const std::vector<SortVariant>& variants_for(int K) {
+  static std::vector<SortVariant> table[17];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    void (*reg[16])(std::vector<SortVariant>&) = {
+        register_k1, register_k2, register_k3, register_k4, register_k5, register_k6,
+        register_k7, register_k8, register_k9, register_k10, register_k11, register_k12,
+        register_k13, register_k14, register_k15, register_k16};
+    for (int k = 1; k <= 16; ++k) reg[k - 1](table[k]);
+  });
+  static const std::vector<SortVariant> empty;
+  return (K >= 1 && K <= 16) ? table[K] : empty;
+}
+
+// Picks the variant a tuning asks for; all-zero (or NULL) = variant 0.
+const SortVariant* pick_variant(int K, const mrx_tuning* t) {
+  const auto& vs = variants_for(K);
+  if (vs.empty()) return nullptr;
+  if (!t || (t->digit_bits == 0 && t->block_threads == 0 && t->items_per_thread == 0)) return &vs[0];
+  if (t->reserved != 0) return nullptr;
+  for (const auto& v : vs)
+    if (v.D == t->digit_bits && v.block == t->block_threads && v.ipt == t->items_per_thread) return &v;
+  return nullptr;
+}
+
+int bits_for(int64_t x) {  // bits needed to represent values 0..x
+  int b = 0;
+  while (x > 0) { ++b; x >>= 1; }
+  return b;
+}
+
+struct Layout {
+  int K = 0, S = 0, P_key = 0, P_mesh = 0;
+  int64_t tiles_sort = 0, tiles_scan = 0;
+  // zeroed region
+  size_t ctl = 0, counters = 0, hist = 0, lookback = 0, used_v = 0, used_g = 0, zero_end = 0;
+  // scratch
+  size_t buf_a = 0, buf_b = 0, o2g = 0, uniq = 0, rep = 0, cmap = 0, total = 0;
+};
+
+Layout make_layout(int64_t n, int K, int32_t nmesh, const SortVariant& v) {
+  Layout L;
+  L.K = K;
+  L.S = K + 1;
+  L.P_key = (32 * K + v.D - 1) / v.D;
+  L.P_mesh = nmesh > 1 ? (bits_for(int64_t(nmesh) - 1) + v.D - 1) / v.D : 0;
+  L.tiles_sort = (n + v.tile() - 1) / v.tile();
+  L.tiles_scan = (n + kScanTile - 1) / kScanTile;
+  const int P = L.P_key + L.P_mesh;
+  size_t off = 0;
+  L.ctl = off;      off = align_up(off + sizeof(Control));
+  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + 2));
+  L.hist = off;     off = align_up(off + sizeof(uint32_t) * size_t(P) * size_t(v.radix()));
+  const int64_t lb_words = std::max<int64_t>({L.tiles_sort * v.radix(), L.tiles_scan, 1});
+  L.lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(lb_words));
+  L.used_v = off;   off = align_up(off + size_t(n));
+  L.used_g = off;   off = align_up(off + size_t(n));
+  L.zero_end = off;
+  L.buf_a = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
+  L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
+  L.o2g = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
+  L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
+  L.rep = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
+  L.cmap = off;     off = align_up(off + sizeof(int32_t) * size_t(n));
+  L.total = off;
+  return L;
+}
+
+// True if [a, a+na) and [b, b+nb) overlap (empty ranges never do).
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+struct Buffer {
+  const void* p;
+  size_t bytes;
+};
+
+// No two listed buffers may overlap.
+bool disjoint(std::initializer_list<Buffer> list) {
+  std::vector<Buffer> v(list);
+  for (size_t i = 0; i < v.size(); ++i)
+    for (size_t j = i + 1; j < v.size(); ++j)
+      if (overlaps(v[i].p, v[i].bytes, v[j].p, v[j].bytes)) return false;
+  return true;
+}
+
+int64_t grid_for(int64_t work, int block, int64_t cap = 8192) {
+  return std::max<int64_t>(1, std::min<int64_t>((work + block - 1) / block, cap));
+}
+
+mrx_status check_launch() {
+  return hipGetLastError() == hipSuccess ? MRX_OK : MRX_ERR_HIP;
+}
+
+// Shared validation of the re-index calls (everything before any HIP call).
+mrx_status validate_common(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, const int32_t* idx,
+                           int64_t num_elems, int32_t arity, const void* out_vtx,
+                           const int32_t* out_idx, const int32_t* old2new, const void* workspace,
+                           size_t workspace_bytes) {
+  if (vtx_bytes < 4 || vtx_bytes > 64 || vtx_bytes % 4 != 0) return MRX_ERR_INVALID_ARGUMENT;
+  if (arity < 1 || num_vtx < 0 || num_elems < 0) return MRX_ERR_INVALID_ARGUMENT;
+  if (num_vtx > kMaxCount) return MRX_ERR_TOO_LARGE;
+  if (num_elems > kMaxCount / arity) return MRX_ERR_TOO_LARGE;
+  const int64_t m = num_elems * arity;
+  if (num_vtx > 0 && (!vtx || !out_vtx || !old2new)) return MRX_ERR_INVALID_ARGUMENT;
+  if (m > 0 && (!idx || !out_idx)) return MRX_ERR_INVALID_ARGUMENT;
+  if (!aligned(vtx, 4) || !aligned(out_vtx, 4) || !aligned(idx, 4) || !aligned(out_idx, 4) ||
+      !aligned(old2new, 4))
+    return MRX_ERR_INVALID_ARGUMENT;
+  if (workspace_bytes > 0 && (!workspace || !aligned(workspace, kAlign))) return MRX_ERR_INVALID_ARGUMENT;
+  return MRX_OK;
+}
+
+}  // namespace
+}  // namespace mrx
+
+using namespace mrx;
+
+extern "C" {
+
+int32_t mrx_abi_version(void) { return MRX_ABI_VERSION; }
+
+const char* mrx_status_string(int32_t s) {
+  switch (s) {
+    case MRX_OK: return "MRX_OK";
+    case MRX_ERR_INVALID_ARGUMENT: return "MRX_ERR_INVALID_ARGUMENT";
+    case MRX_ERR_WORKSPACE_TOO_SMALL: return "MRX_ERR_WORKSPACE_TOO_SMALL";
+    case MRX_ERR_INDEX_OUT_OF_RANGE: return "MRX_ERR_INDEX_OUT_OF_RANGE";
+    case MRX_ERR_TOO_LARGE: return "MRX_ERR_TOO_LARGE";
+    case MRX_ERR_HIP: return "MRX_ERR_HIP";
+    case MRX_ERR_UNSUPPORTED: return "MRX_ERR_UNSUPPORTED";
+    case MRX_ERR_INTERNAL: return "MRX_ERR_INTERNAL";
+    default: return "MRX_UNKNOWN_STATUS";
+  }
+}
+
+int32_t mrx_tuning_count(int32_t vtx_bytes) {
+  if (vtx_bytes < 4 || vtx_bytes > 64 || vtx_bytes % 4) return 0;
+  return int32_t(variants_for(vtx_bytes / 4).size());
+}
+
+mrx_status mrx_tuning_get(int32_t vtx_bytes, int32_t i, mrx_tuning* out) {
+  if (!out || i < 0 || i >= mrx_tuning_count(vtx_bytes)) return MRX_ERR_INVALID_ARGUMENT;
+  const SortVariant& v = variants_for(vtx_bytes / 4)[i];
+  out->digit_bits = v.D;
+  out->block_threads = v.block;
+  out->items_per_thread = v.ipt;
+  out->reserved = 0;
+  return MRX_OK;
+}
+
+mrx_status mrx_profile_enable(int32_t on) {
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  if (on) {
+    p.recs.clear();
+    p.next = 0;
+  }
+  p.on = on != 0;
+  return MRX_OK;
+}
+
+// Named marks, each followed by the mark that ends its kernel.
+static std::vector<std::pair<size_t, size_t>> prof_pairs(const Profiler& p) {
+  std::vector<std::pair<size_t, size_t>> out;
+  for (size_t i = 0; i + 1 < p.recs.size(); ++i)
+    if (p.recs[i].name) out.emplace_back(i, i + 1);
+  return out;
+}
+
+int32_t mrx_profile_count(void) {
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  return int32_t(prof_pairs(p).size());
+}
+
+mrx_status mrx_profile_get(int32_t i, const char** name, float* ms) {
+  Profiler& p = profiler();
+  ProfRecord a, b;
+  {
+    std::lock_guard<std::mutex> g(p.mu);
+    const auto pairs = prof_pairs(p);
+    if (i < 0 || size_t(i) >= pairs.size() || !ms) return MRX_ERR_INVALID_ARGUMENT;
+    a = p.recs[pairs[size_t(i)].first];
+    b = p.recs[pairs[size_t(i)].second];
+  }
+  if (name) *name = a.name;
+  if (hipEventSynchronize(b.event) != hipSuccess) return MRX_ERR_HIP;
+  return hipEventElapsedTime(ms, a.event, b.event) == hipSuccess ? MRX_OK : MRX_ERR_HIP;
+}
+
+mrx_status mrx_reindex_workspace_size(int64_t num_vtx, int32_t vtx_bytes, int64_t num_idx,
+                                      int32_t num_meshes, const mrx_tuning* tuning, size_t* bytes) {
+  if (!bytes) return MRX_ERR_INVALID_ARGUMENT;
+  if (vtx_bytes < 4 || vtx_bytes > 64 || vtx_bytes % 4 != 0) return MRX_ERR_INVALID_ARGUMENT;
+  if (num_vtx < 0 || num_idx < 0 || num_meshes < 1) return MRX_ERR_INVALID_ARGUMENT;
+  if (num_vtx > kMaxCount || num_idx > kMaxCount) return MRX_ERR_TOO_LARGE;
+  const SortVariant* v = pick_variant(vtx_bytes / 4, tuning);
+  if (!v) return MRX_ERR_UNSUPPORTED;
+  *bytes = make_layout(num_vtx, vtx_bytes / 4, num_meshes, *v).total;
+  return MRX_OK;
+}
+
+mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, const int32_t* idx,
+                            int64_t num_elems, int32_t arity, void* out_vtx, int32_t* out_idx,
+                            int32_t* old2new, int32_t* new2old, int64_t* out_num_vtx,
+                            int32_t* dev_status, void* workspace, size_t workspace_bytes,
+                            const mrx_tuning* tuning, void* stream_) {
+  mrx_status st = validate_common(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx,
+                                  old2new, workspace, workspace_bytes);
+  if (st != MRX_OK) return st;
+  if (!out_num_vtx || !aligned(out_num_vtx, 8) || !aligned(new2old, 4) || !aligned(dev_status, 4))
+    return MRX_ERR_INVALID_ARGUMENT;
+  const int K = vtx_bytes / 4;
+  const SortVariant* vp = pick_variant(K, tuning);
+  if (!vp) return MRX_ERR_UNSUPPORTED;
+  const SortVariant& v = *vp;
+  const int64_t n = num_vtx, m = num_elems * arity;
+  const Layout L = make_layout(n, K, 1, v);
+  if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
+  const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4;
+  if (!disjoint({{vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
+                 {out_num_vtx, 8}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
+                 {idx == out_idx ? nullptr : idx, ib}}) ||
+      !disjoint({{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
+                 {out_num_vtx, 8}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total}}))
+    return MRX_ERR_INVALID_ARGUMENT;
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
+  uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
+  uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
+  int32_t* o2g = reinterpret_cast<int32_t*>(ws + L.o2g);
+  uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
+  int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
+  int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
+  int32_t* status = dev_status ? dev_status : &ctl->status;
+
+  // per-call state: look-back words, tile counters, histograms, flags, G
+  prof_mark("fill_zero", s);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx);
+  // Step 1: mark referenced vertices (and report out-of-range entries)
+  if (m > 0) {
+    prof_mark("mark_used", s);
+    hipLaunchKernelGGL((k_mark_used<false>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+                       nullptr, nullptr, 0, used_v, status);
+  }
+  if (n > 0) {
+    // Step 2: stable LSD radix sort of (record, id | used << 31)
+    prof_mark("histogram", s);
+    v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    prof_mark("scan_buckets", s);
+    v.scan(hist, L.P_key, s);
+    const uint32_t* src = static_cast<const uint32_t*>(vtx);
+    int cur = 0;
+    for (int p = 0; p < L.P_key; ++p) {
+      SortPassArgs a{};
+      a.src = src;
+      a.dst = buf[cur];
+      a.used = used_v;
+      a.bucket_base = hist + size_t(p) * v.radix();
+      a.lookback = lookback;
+      a.tile_counter = counters + p;
+      a.ctl = ctl;
+      a.status = status;
+      a.n = n;
+      const int bit = p * v.D;
+      a.word_lo = K - 1 - bit / 32;
+      a.word_hi = a.word_lo - 1;
+      a.shift = bit % 32;
+      a.tag = uint32_t(p + 1);
+      prof_mark(p == 0 ? "onesweep_first" : "onesweep", s);
+      v.pass(a, p == 0 ? kPassFirst : kPassKey, L.tiles_sort, s);
+      src = buf[cur];
+      cur ^= 1;
+    }
+    // Step 2 flags + prefix sum, Step 3/4 scatters
+    FlagScanArgs f{};
+    f.sorted = src;
+    f.n = n;
+    f.o2g = o2g;
+    f.uniq = uniq;
+    f.rep = rep;
+    f.used_g = used_g;
+    f.lookback = lookback;
+    f.tile_counter = counters + L.P_key;
+    f.ctl = ctl;
+    f.status = status;
+    f.tag = uint32_t(L.P_key + 1);
+    prof_mark("flag_scan", s);
+    v.flag_scan(f, false, L.tiles_scan, s);
+    // Step 3 on used groups only: compaction
+    CompactArgs c{};
+    c.used_g = used_g;
+    c.uniq = uniq;
+    c.rep = rep;
+    c.K = K;
+    c.out_vtx = static_cast<uint32_t*>(out_vtx);
+    c.new2old = new2old;
+    c.cmap = cmap;
+    c.out_num = out_num_vtx;
+    c.cap = n;
+    c.lookback = lookback;
+    c.tile_counter = counters + L.P_key + 1;
+    c.ctl = ctl;
+    c.status = status;
+    c.tag = uint32_t(L.P_key + 2);
+    prof_mark("compact", s);
+    hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
+    prof_mark("old2new", s);
+    hipLaunchKernelGGL((k_old2new<false>), dim3(grid_for(n, 256)), dim3(256), 0, s, o2g, cmap, n, n,
+                       nullptr, nullptr, 0, old2new);
+  }
+  // Step 4: remap the index array
+  if (m > 0) {
+    prof_mark("remap", s);
+    hipLaunchKernelGGL((k_remap<false>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+                       nullptr, nullptr, 0, old2new, out_idx);
+  }
+  prof_mark(nullptr, s);
+  return check_launch();
+}
+
+mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets, int64_t total_vtx,
+                                    int32_t vtx_bytes, const int32_t* idx, const int64_t* elem_offsets,
+                                    int64_t total_elems, int32_t arity, int32_t num_meshes,
+                                    void* out_vtx, int64_t* out_vtx_offsets, int32_t* out_idx,
+                                    int32_t* old2new, int32_t* new2old, int32_t* dev_status,
+                                    void* workspace, size_t workspace_bytes,
+                                    const mrx_tuning* tuning, void* stream_) {
+  mrx_status st = validate_common(vtx, total_vtx, vtx_bytes, idx, total_elems, arity, out_vtx, out_idx,
+                                  old2new, workspace, workspace_bytes);
+  if (st != MRX_OK) return st;
+  if (num_meshes < 1 || !vtx_offsets || !elem_offsets || !out_vtx_offsets ||
+      !aligned(vtx_offsets, 8) || !aligned(elem_offsets, 8) || !aligned(out_vtx_offsets, 8) ||
+      !aligned(new2old, 4) || !aligned(dev_status, 4))
+    return MRX_ERR_INVALID_ARGUMENT;
+  const int K = vtx_bytes / 4;
+  const SortVariant* vp = pick_variant(K, tuning);
+  if (!vp) return MRX_ERR_UNSUPPORTED;
+  const SortVariant& v = *vp;
+  const int64_t n = total_vtx, m = total_elems * arity;
+  const Layout L = make_layout(n, K, num_meshes, v);
+  if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
+  const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4,
+               ob = size_t(num_meshes + 1) * 8;
+  if (!disjoint({{vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
+                 {out_vtx_offsets, ob}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
+                 {vtx_offsets, ob}, {elem_offsets, ob}, {idx == out_idx ? nullptr : idx, ib}}) ||
+      !disjoint({{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
+                 {out_vtx_offsets, ob}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
+                 {vtx_offsets, ob}, {elem_offsets, ob}}))
+    return MRX_ERR_INVALID_ARGUMENT;
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
+  uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
+  uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
+  int32_t* o2g = reinterpret_cast<int32_t*>(ws + L.o2g);
+  uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
+  int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
+  int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
+  int32_t* status = dev_status ? dev_status : &ctl->status;
+  const int P = L.P_key + L.P_mesh;
+
+  prof_mark("fill_zero", s);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status,
+                     static_cast<int64_t*>(nullptr));
+  if (m > 0) {
+    prof_mark("mark_used", s);
+    hipLaunchKernelGGL((k_mark_used<true>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+                       vtx_offsets, elem_offsets, num_meshes, used_v, status);
+  }
+  if (n > 0) {
+    prof_mark("histogram", s);
+    v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    prof_mark("mesh_histogram", s);
+    v.mesh_hist(vtx_offsets, num_meshes, L.P_mesh, hist + size_t(L.P_key) * v.radix(), s);
+    prof_mark("scan_buckets", s);
+    v.scan(hist, P, s);
+    const uint32_t* src = static_cast<const uint32_t*>(vtx);
+    int cur = 0;
+    for (int p = 0; p < P; ++p) {
+      SortPassArgs a{};
+      a.src = src;
+      a.dst = buf[cur];
+      a.used = used_v;
+      a.bucket_base = hist + size_t(p) * v.radix();
+      a.lookback = lookback;
+      a.tile_counter = counters + p;
+      a.ctl = ctl;
+      a.status = status;
+      a.n = n;
+      a.mesh_off = vtx_offsets;
+      a.nmesh = num_meshes;
+      a.tag = uint32_t(p + 1);
+      int mode = kPassKey;
+      if (p < L.P_key) {
+        const int bit = p * v.D;
+        a.word_lo = K - 1 - bit / 32;
+        a.word_hi = a.word_lo - 1;
+        a.shift = bit % 32;
+        if (p == 0) mode = kPassFirst;
+      } else {
+        a.word_lo = 0;
+        a.word_hi = -1;
+        a.shift = (p - L.P_key) * v.D;
+        mode = kPassMesh;
+      }
+      prof_mark(mode == kPassFirst ? "onesweep_first" : mode == kPassMesh ? "onesweep_mesh" : "onesweep", s);
+      v.pass(a, mode, L.tiles_sort, s);
+      src = buf[cur];
+      cur ^= 1;
+    }
+    FlagScanArgs f{};
+    f.sorted = src;
+    f.n = n;
+    f.o2g = o2g;
+    f.uniq = uniq;
+    f.rep = rep;
+    f.used_g = used_g;
+    f.lookback = lookback;
+    f.tile_counter = counters + P;
+    f.ctl = ctl;
+    f.status = status;
+    f.mesh_off = vtx_offsets;
+    f.nmesh = num_meshes;
+    f.tag = uint32_t(P + 1);
+    prof_mark("flag_scan", s);
+    v.flag_scan(f, true, L.tiles_scan, s);
+    CompactArgs c{};
+    c.used_g = used_g;
+    c.uniq = uniq;
+    c.rep = rep;
+    c.K = K;
+    c.out_vtx = static_cast<uint32_t*>(out_vtx);
+    c.new2old = new2old;
+    c.cmap = cmap;
+    c.out_num = &ctl->num_used;
+    c.cap = n;
+    c.lookback = lookback;
+    c.tile_counter = counters + P + 1;
+    c.ctl = ctl;
+    c.status = status;
+    c.tag = uint32_t(P + 2);
+    prof_mark("compact", s);
+    hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
+    prof_mark("batch_offsets", s);
+    hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets,
+                       num_meshes, static_cast<const uint32_t*>(src), int32_t(L.S), o2g, cmap, ctl,
+                       &ctl->num_used, n, out_vtx_offsets);
+    prof_mark("old2new", s);
+    hipLaunchKernelGGL((k_old2new<true>), dim3(grid_for(n, 256)), dim3(256), 0, s, o2g, cmap, n, n,
+                       vtx_offsets, out_vtx_offsets, num_meshes, old2new);
+    if (new2old) {
+      prof_mark("localize_new2old", s);
+      hipLaunchKernelGGL(k_localize_new2old, dim3(grid_for(n, 256)), dim3(256), 0, s, new2old,
+                         &ctl->num_used, vtx_offsets, num_meshes);
+    }
+  } else {
+    prof_mark("batch_offsets", s);
+    hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets,
+                       num_meshes, static_cast<const uint32_t*>(nullptr), int32_t(L.S), o2g, cmap, ctl,
+                       &ctl->num_used, n, out_vtx_offsets);
+  }
+  if (m > 0) {
+    prof_mark("remap", s);
+    hipLaunchKernelGGL((k_remap<true>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+                       vtx_offsets, elem_offsets, num_meshes, old2new, out_idx);
+  }
+  prof_mark(nullptr, s);
+  return check_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Instantiates the sort and flag-scan kernels for one record width.
+// Built once per K with -DMRX_INST_K=<K>.
+#include "registry.hpp"
+
+#ifndef MRX_INST_K
+#error "MRX_INST_K must be defined"
+#endif
+
+#define MRX_CAT2(a, b) a##b
+#define MRX_CAT(a, b) MRX_CAT2(a, b)
+
+namespace mrx {
+namespace {
+
+constexpr int K = MRX_INST_K;
+
+template <int D, int BLOCK, int IPT>
+void launch_pass(const SortPassArgs& a, int mode, int64_t grid, hipStream_t s) {
+  if (grid <= 0) return;
+  switch (mode) {
+    case kPassFirst:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassFirst>), dim3(grid), dim3(BLOCK), 0, s, a);
+      break;
+    case kPassKey:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassKey>), dim3(grid), dim3(BLOCK), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassMesh>), dim3(grid), dim3(BLOCK), 0, s, a);
+      break;
+  }
+}
+
+template <int D>
+void launch_hist(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) {
+  constexpr int B = 256, ITEMS = 16;
+  const int64_t grid = (n + B * ITEMS - 1) / (B * ITEMS);
+  if (grid > 0) hipLaunchKernelGGL((k_histogram<K, D, B, ITEMS>), dim3(grid), dim3(B), 0, s, vtx, n, hist);
+}
+
+template <int D>
+void launch_mesh_hist(const int64_t* off, int32_t nmesh, int32_t passes, uint32_t* hist, hipStream_t s) {
+  if (nmesh <= 0 || passes <= 0) return;
+  hipLaunchKernelGGL((k_mesh_histogram<D>), dim3((nmesh + 255) / 256), dim3(256), 0, s, off, nmesh,
+                     passes, hist);
+}
+
+template <int D>
+void launch_scan(uint32_t* hist, int32_t passes, hipStream_t s) {
+  if (passes > 0) hipLaunchKernelGGL((k_scan_buckets<D, 256>), dim3(passes), dim3(256), 0, s, hist);
+}
+
+void launch_flag_scan(const FlagScanArgs& a, bool batched, int64_t grid, hipStream_t s) {
+  if (grid <= 0) return;
+  if (batched)
+    hipLaunchKernelGGL((k_flag_scan<K, kScanBlock, kScanIpt, true>), dim3(grid), dim3(kScanBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_flag_scan<K, kScanBlock, kScanIpt, false>), dim3(grid), dim3(kScanBlock), 0, s, a);
+}
+
+template <int D, int BLOCK, int IPT>
+SortVariant make() {
+  SortVariant v;
+  v.K = K;
+  v.D = D;
+  v.block = BLOCK;
+  v.ipt = IPT;
+  v.pass = &launch_pass<D, BLOCK, IPT>;
+  v.hist = &launch_hist<D>;
+  v.mesh_hist = &launch_mesh_hist<D>;
+  v.scan = &launch_scan<D>;
+  v.flag_scan = &launch_flag_scan;
+  return v;
+}
+
+}  // namespace
+
+void MRX_CAT(register_k, MRX_INST_K)(std::vector<SortVariant>& out) {
+  out.push_back(make<8, 256, default_ipt(K)>());  // variant 0: default
+#if MRX_INST_K == 2 || MRX_INST_K == 3
+  out.push_back(make<8, 512, 16>());
+  out.push_back(make<8, 256, 12>());
+  out.push_back(make<8, 512, 8>());
+#elif MRX_INST_K == 8
+  out.push_back(make<8, 512, 8>());
+  out.push_back(make<8, 256, 6>());
+#endif
+}
+
+}  // namespace mrx

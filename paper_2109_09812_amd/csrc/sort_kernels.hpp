@@ -1,0 +1,308 @@
+// LSD radix sort of (vertex record, original id) pairs — the key-value sort
+// of Section 2, Step 2 — as one-sweep digit passes with decoupled look-back.
+//
+// Key order: record words w0..w{K-1} compared lexicographically, w0 most
+// significant, unsigned. LSD pass p handles key bits [p*D, p*D + D) counted
+// from the least significant bit of w{K-1}. Every pass is stable, so equal
+// records end up in ascending original-id order: the first element of every
+// run of equal records is the copy with the smallest original id.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace mrx {
+
+enum PassMode : int { kPassFirst = 0, kPassKey = 1, kPassMesh = 2 };
+
+struct SortPassArgs {
+  const uint32_t* src;          // first pass: vertex records (K words); else elements (K+1 words)
+  uint32_t* dst;                // elements (K+1 words)
+  const uint8_t* used;          // first pass: 1 if some index entry references the vertex
+  const uint32_t* bucket_base;  // [RADIX] start of each digit's bucket in dst
+  uint64_t* lookback;           // [tiles][RADIX]
+  uint32_t* tile_counter;
+  Control* ctl;
+  int32_t* status;
+  const int64_t* mesh_off;      // mesh passes: [nmesh+1] vertex offsets
+  int32_t nmesh;
+  int32_t word_lo;              // key word holding the digit's low bits
+  int32_t word_hi;              // next more significant word (-1: none)
+  int32_t shift;                // bit offset of the digit inside word_lo (mesh passes: inside the mesh id)
+  int64_t n;
+  uint32_t tag;
+};
+
+template <int D>
+__device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift) {
+  uint32_t x = lo >> shift;
+  if constexpr (32 % D != 0) {
+    if (shift + D > 32) x |= hi << (32 - shift);  // digit spans two words
+  }
+  return x & ((1u << D) - 1u);
+}
+
+// ----------------------------------------------------------------------------
+// Digit histograms of every key pass in one read of the records.
+// hist[p * RADIX + b] += number of records whose pass-p digit is b.
+template <int K, int D, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t* __restrict__ vtx, int64_t n,
+                                                     uint32_t* __restrict__ hist) {
+  constexpr int RADIX = 1 << D;
+  constexpr int P = (32 * K + D - 1) / D;
+  __shared__ uint32_t s_h[P * RADIX];
+  for (int i = threadIdx.x; i < P * RADIX; i += BLOCK) s_h[i] = 0;
+  __syncthreads();
+
+  // Runs of equal digits are counted in registers first: skewed digits (the
+  // exponent byte of float coordinates) would otherwise serialise on one
+  // LDS address.
+  uint32_t last[P], run[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
+
+  const int64_t base = int64_t(blockIdx.x) * (BLOCK * ITEMS);
+  for (int it = 0; it < ITEMS; ++it) {
+    const int64_t pos = base + int64_t(it) * BLOCK + threadIdx.x;
+    if (pos >= n) break;
+    uint32_t w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[k] = vtx[pos * K + k];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int bit = p * D;
+      const int wi = K - 1 - bit / 32;
+      const int hi = wi - 1;
+      const uint32_t d = digit_of<D>(w[wi], hi >= 0 ? w[hi >= 0 ? hi : 0] : 0u, bit % 32);
+      if (run[p] != 0 && d == last[p]) {
+        ++run[p];
+      } else {
+        if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
+        last[p] = d;
+        run[p] = 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P * RADIX; i += BLOCK)
+    if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// Histograms of the mesh-id passes of a batch: mesh b contributes its vertex
+// count to digit (b >> shift_q) of mesh pass q.
+template <int D>
+__global__ void k_mesh_histogram(const int64_t* __restrict__ off, int32_t nmesh, int32_t mesh_passes,
+                                 uint32_t* __restrict__ hist) {
+  constexpr int RADIX = 1 << D;
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nmesh) return;
+  const uint32_t cnt = uint32_t(off[b + 1] - off[b]);
+  if (cnt == 0) return;
+  for (int q = 0; q < mesh_passes; ++q)
+    atomicAdd(&hist[q * RADIX + ((uint32_t(b) >> (q * D)) & (RADIX - 1))], cnt);
+}
+
+// Exclusive scan of each pass's RADIX counts, in place (one block per pass).
+template <int D, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_scan_buckets(uint32_t* __restrict__ hist) {
+  constexpr int RADIX = 1 << D;
+  constexpr int BPT = (RADIX + BLOCK - 1) / BLOCK;
+  __shared__ uint32_t s_wave[BLOCK / kWave];
+  uint32_t* h = hist + int64_t(blockIdx.x) * RADIX;
+  uint32_t c[BPT];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int bin = threadIdx.x * BPT + k;
+    c[k] = bin < RADIX ? h[bin] : 0u;
+    sum += c[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<BLOCK>(sum, s_wave, &total);
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int bin = threadIdx.x * BPT + k;
+    if (bin < RADIX) h[bin] = run;
+    run += c[k];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// One LSD digit pass.
+//
+// Tile layout: wave w of the block owns positions
+//   tile*TILE + w*64*IPT + j*64 + lane,   j = 0..IPT-1,
+// so every load instruction is coalesced and the (wave, j, lane) order is the
+// input order. Ranking is stable: within a wave the D digit bits are matched
+// with ballots, the lowest lane of each equal-digit group bumps a per-wave
+// LDS counter by the group size, and every lane adds the number of peers on
+// lower lanes. Wave counters are then turned into wave-exclusive offsets, a
+// block scan gives each digit's start inside the tile, and a decoupled
+// look-back over preceding tiles (one word per (tile, digit)) gives the
+// digit's global offset. Elements are reordered through LDS into digit
+// order, one 32-bit word plane at a time, so each thread writes runs of
+// consecutive addresses.
+template <int K, int D, int BLOCK, int IPT, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
+  constexpr int S = K + 1;
+  constexpr int RADIX = 1 << D;
+  constexpr uint32_t MASK = RADIX - 1;
+  constexpr int WAVES = BLOCK / kWave;
+  constexpr int TILE = BLOCK * IPT;
+  constexpr int BPT = (RADIX + BLOCK - 1) / BLOCK;
+  static_assert(D <= 16, "digits are staged as 16-bit values");
+
+  __shared__ uint32_t s_hist[WAVES * RADIX];
+  __shared__ uint32_t s_start[RADIX];
+  __shared__ uint32_t s_base[RADIX];
+  __shared__ uint32_t s_buf[2][TILE];
+  __shared__ uint16_t s_dig[TILE];
+  __shared__ uint32_t s_wave[WAVES];
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = tid / kWave;
+  for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_hist[i] = 0;
+  const uint32_t tile = claim_tile(a.tile_counter, &s_tile);  // synchronises the block
+  const int64_t tile_base = int64_t(tile) * TILE;
+  const int64_t n = a.n;
+  const int valid_count = int(min(int64_t(TILE), n - tile_base));
+
+  // ---- load
+  uint32_t v[IPT][S];
+  const int64_t wave_base = tile_base + int64_t(wave) * (kWave * IPT) + lane;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t pos = wave_base + j * kWave;
+    if (pos < n) {
+      if constexpr (MODE == kPassFirst) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[j][k] = a.src[pos * K + k];
+        v[j][K] = uint32_t(pos) | (a.used[pos] ? 0x80000000u : 0u);
+      } else {
+        load_words<S>(a.src + pos * S, v[j]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < S; ++k) v[j][k] = 0;
+    }
+  }
+
+  // ---- digits
+  uint32_t dig[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if constexpr (MODE == kPassMesh) {
+      const int64_t pos = wave_base + j * kWave;
+      const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu)) : 0u;
+      dig[j] = (m >> a.shift) & MASK;
+    } else {
+      const uint32_t lo = pick_word<S>(v[j], a.word_lo);
+      const uint32_t hi = (32 % D != 0 && a.word_hi >= 0) ? pick_word<S>(v[j], a.word_hi) : 0u;
+      dig[j] = digit_of<D>(lo, hi, a.shift);
+    }
+  }
+
+  // ---- stable rank inside the wave
+  uint32_t* my_hist = s_hist + wave * RADIX;
+  uint32_t rank[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const bool valid = (wave_base + j * kWave) < n;
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const bool bit = (dig[j] >> b) & 1u;
+      const uint64_t m = ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const int leader = peers ? (__ffsll((unsigned long long)peers) - 1) : lane;
+    const uint32_t below = uint32_t(popc64(peers & lanemask_lt()));
+    uint32_t base = 0;
+    if (valid && lane == leader) base = atomicAdd(&my_hist[dig[j]], uint32_t(popc64(peers)));
+    base = __shfl(base, leader, kWave);
+    rank[j] = base + below;
+  }
+  __syncthreads();
+
+  // ---- per-digit tile totals; wave counters become wave-exclusive offsets
+  uint32_t tot[BPT];
+  uint32_t my_sum = 0;
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int bin = tid * BPT + k;
+    uint32_t run = 0;
+    if (bin < RADIX) {
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = s_hist[w * RADIX + bin];
+        s_hist[w * RADIX + bin] = run;
+        run += c;
+      }
+      // publish this tile's count as early as possible
+      lb_store(a.lookback + int64_t(tile) * RADIX + bin,
+               lb_pack(tile == 0 ? kLbInclusive : kLbAggregate, a.tag, run));
+    }
+    tot[k] = run;
+    my_sum += run;
+  }
+  uint32_t tile_total;
+  uint32_t start = block_exclusive_scan<BLOCK>(my_sum, s_wave, &tile_total);
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int bin = tid * BPT + k;
+    if (bin < RADIX) {
+      uint32_t prev = 0;
+      if (tile != 0) {
+        prev = lookback_exclusive(a.lookback + bin, tile, RADIX, a.tag, a.ctl, a.status);
+        lb_store(a.lookback + int64_t(tile) * RADIX + bin, lb_pack(kLbInclusive, a.tag, prev + tot[k]));
+      }
+      s_start[bin] = start;
+      s_base[bin] = a.bucket_base[bin] + prev - start;  // wraps; base + local position is exact
+    }
+    start += tot[k];
+  }
+  __syncthreads();
+
+  // ---- positions inside the tile (digit-major, stable)
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if ((wave_base + j * kWave) < n) {
+      rank[j] += s_start[dig[j]] + my_hist[dig[j]];
+      s_dig[rank[j]] = uint16_t(dig[j]);
+    }
+  }
+  __syncthreads();
+  uint32_t opos[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int q = r * BLOCK + tid;
+    opos[r] = q < valid_count ? s_base[s_dig[q]] + uint32_t(q) : 0xFFFFFFFFu;
+  }
+
+  // ---- reorder one word plane at a time through LDS (double-buffered)
+#pragma unroll
+  for (int w = 0; w < S; ++w) {
+    uint32_t* buf = s_buf[w & 1];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      if ((wave_base + j * kWave) < n) buf[rank[j]] = v[j][w];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const int q = r * BLOCK + tid;
+      if (q < valid_count) v[r][w] = buf[q];
+    }
+  }
+
+  // ---- scatter: consecutive q of one digit go to consecutive addresses
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    if (int64_t(opos[r]) < n) store_words<S>(a.dst + int64_t(opos[r]) * S, v[r]);
+  }
+}
+
+}  // namespace mrx

@@ -1,0 +1,158 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments before enqueuing anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2109_09812_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "meshrx.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrx_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.load()
+    names = declared_symbols()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_status_strings():
+    lib = _lib.load()
+    assert lib.mrx_abi_version() == 1
+    for code, name in [(0, "MRX_OK"), (1, "MRX_ERR_INVALID_ARGUMENT"), (2, "MRX_ERR_WORKSPACE_TOO_SMALL"),
+                       (3, "MRX_ERR_INDEX_OUT_OF_RANGE"), (4, "MRX_ERR_TOO_LARGE"), (5, "MRX_ERR_HIP"),
+                       (6, "MRX_ERR_UNSUPPORTED"), (7, "MRX_ERR_INTERNAL")]:
+        assert _lib.status_string(code) == name
+    assert _lib.status_string(99) == "MRX_UNKNOWN_STATUS"
+
+
+def test_tuning_enumeration():
+    lib = _lib.load()
+    for vb in range(4, 65, 4):
+        ts = _lib.tunings(vb)
+        assert len(ts) >= 1
+        assert ts[0].digit_bits >= 8 and ts[0].block_threads % 64 == 0
+        assert len({t.as_tuple() for t in ts}) == len(ts)
+    for bad in (0, 2, 6, 68, -4):
+        assert lib.mrx_tuning_count(bad) == 0
+    t = _lib.Tuning()
+    assert lib.mrx_tuning_get(12, 99, ctypes.byref(t)) == _lib.MRX_ERR_INVALID_ARGUMENT
+
+
+def _ws(n, vb, m, meshes=1, tuning=None):
+    out = ctypes.c_size_t(0)
+    st = _lib.load().mrx_reindex_workspace_size(n, vb, m, meshes, _lib.make_tuning(tuning),
+                                                ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size():
+    st, small = _ws(1000, 12, 3000)
+    assert st == 0 and small > 0 and small % 256 == 0
+    st, big = _ws(26_398_316, 12, 25_141_254)
+    assert st == 0 and big > 2 * 26_398_316 * 16
+    st, batched = _ws(1000, 12, 3000, 4096)
+    assert st == 0 and batched >= small
+    assert _ws(-1, 12, 0)[0] == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert _ws(10, 6, 0)[0] == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert _ws(10, 12, 0, 0)[0] == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert _ws(2**31, 12, 0)[0] == _lib.MRX_ERR_TOO_LARGE
+    assert _ws(10, 12, 0, 1, (7, 256, 16))[0] == _lib.MRX_ERR_UNSUPPORTED
+
+
+# Fake, never-dereferenced device addresses: every call below must be
+# rejected by host-side validation before anything is enqueued.
+A = 0x10000000
+B = 0x20000000
+C = 0x30000000
+D = 0x40000000
+E = 0x50000000
+F = 0x60000000
+W = 0x70000000
+
+
+def _call(**kw):
+    args = dict(vtx=A, n=100, vb=12, idx=B, ne=10, arity=3, out_vtx=C, out_idx=D, old2new=E,
+                new2old=F, out_num=0x7F000000, status=0x7F000100, ws=W, wsb=1 << 30, tuning=None,
+                stream=None)
+    args.update(kw)
+    return _lib.load().mrx_reindex_mesh(
+        args["vtx"], args["n"], args["vb"], args["idx"], args["ne"], args["arity"], args["out_vtx"],
+        args["out_idx"], args["old2new"], args["new2old"], args["out_num"], args["status"], args["ws"],
+        args["wsb"], _lib.make_tuning(args["tuning"]), args["stream"])
+
+
+@pytest.mark.parametrize("kw,expected", [
+    (dict(vb=6), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(vb=0), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(vb=68), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(arity=0), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(n=-1), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(ne=-1), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(n=2**31), _lib.MRX_ERR_TOO_LARGE),
+    (dict(ne=2**30, arity=3), _lib.MRX_ERR_TOO_LARGE),
+    (dict(vtx=None), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(out_vtx=None), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(old2new=None), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(idx=None), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(out_idx=None), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(out_num=None), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(vtx=A + 2), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(ws=W + 64), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(out_num=0x7F000004), _lib.MRX_ERR_INVALID_ARGUMENT),
+    (dict(wsb=1024), _lib.MRX_ERR_WORKSPACE_TOO_SMALL),
+    (dict(ws=None, wsb=0), _lib.MRX_ERR_WORKSPACE_TOO_SMALL),
+    (dict(out_vtx=A + 4), _lib.MRX_ERR_INVALID_ARGUMENT),      # overlaps vtx
+    (dict(old2new=C + 8), _lib.MRX_ERR_INVALID_ARGUMENT),      # overlaps out_vtx
+    (dict(out_idx=E), _lib.MRX_ERR_INVALID_ARGUMENT),          # out_idx == old2new
+    (dict(new2old=W + 4096), _lib.MRX_ERR_INVALID_ARGUMENT),   # inside the workspace
+    (dict(tuning=(9, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
+])
+def test_reindex_rejects_bad_arguments(kw, expected):
+    assert _call(**kw) == expected
+
+
+def test_workspace_one_byte_short():
+    st, need = _ws(100, 12, 30)
+    assert st == 0
+    assert _call(wsb=need - 1) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_batched_rejects_bad_arguments():
+    lib = _lib.load()
+    f = lib.mrx_reindex_mesh_batched
+    base = [A, 0x7E000000, 100, 12, B, 0x7E100000, 10, 3, 4, C, 0x7E200000, D, E, F, 0x7F000100, W, 1 << 30,
+            None, None]
+    assert f(*base[:8], 0, *base[9:]) == _lib.MRX_ERR_INVALID_ARGUMENT          # no meshes
+    bad = list(base); bad[1] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no vtx_offsets
+    bad = list(base); bad[10] = 0x7E200004
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # misaligned offsets
+    bad = list(base); bad[16] = 256
+    assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_gather_rejects_bad_arguments():
+    lib = _lib.load()
+    g = lib.mrx_gather_attrs
+    assert g(A, 10, 0, 0, B, 5, C, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT   # channels
+    assert g(A, 10, 16, 2, B, 5, C, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT  # dtype
+    assert g(A, 10, 16, 0, B, 5, None, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert g(A + 4, 10, 16, 0, B, 5, C, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert g(A, 10, 16, 0, B, 5, A + 64, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT  # overlap
+    assert g(A, 2**31, 16, 0, B, 5, C, None, None) == _lib.MRX_ERR_TOO_LARGE
+    assert g(A, 10, 16, 0, B, 0, C, None, None) == _lib.MRX_OK                     # nothing to do
+    gb = lib.mrx_gather_attrs_backward
+    assert gb(A, 5, 16, 0, B, 10, None, 1, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert gb(A, 5, 16, 0, B, 10, C + 4, 1, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT
+    assert gb(A, 5, 16, 1, B, 10, A, 1, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT   # overlap

@@ -1,0 +1,130 @@
+"""GPU parity of the batched (segmented) re-index: one launch sequence for
+many independent meshes must equal the per-mesh oracle, never merge equal
+vertices of different meshes, and replay correctly from a HIP graph."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(b: meshgen.Batch):
+    return (torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)).to(DEV),
+            torch.from_numpy(b.vtx_offsets).to(DEV),
+            torch.from_numpy(b.idx).to(DEV),
+            torch.from_numpy(b.elem_offsets).to(DEV))
+
+
+def check_batch(b: meshgen.Batch, res):
+    ov, ooff, oi, o2n, n2o = oracle.reindex_batched(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
+    assert np.array_equal(res.out_vtx_offsets.cpu().numpy(), ooff)
+    assert np.array_equal(res.out_vtx.cpu().numpy().view(np.uint32), ov)
+    assert np.array_equal(res.out_idx.cpu().numpy(), oi)
+    assert np.array_equal(res.old2new.cpu().numpy(), o2n)
+    assert np.array_equal(res.new2old.cpu().numpy(), n2o)
+    assert np.array_equal(np.diff(ooff), b.expected_unique)
+
+
+@pytest.mark.parametrize("meshes,hi,seed", [(1, 3000, 1), (7, 3000, 2), (64, 20_000, 3), (300, 5_000, 4)])
+def test_batched_matches_per_mesh_oracle(meshes, hi, seed):
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(meshes, 100, hi, 0.05, 900 + seed)
+    _say("batch", meshes, "meshes", b.vtx.shape[0], "vertices")
+    res = mrx.reindex_mesh_batched(*to_dev(b))
+    check_batch(b, res)
+
+
+def test_cross_mesh_vertices_never_merge():
+    import paper_2109_09812_amd as mrx
+    one = meshgen.batched(1, 500, 501, 0.05, 31)
+    m = one.mesh(0)
+    # the same mesh three times: bitwise-equal vertices in every mesh
+    vtx = np.concatenate([m.vtx] * 3)
+    idx = np.concatenate([m.idx] * 3)
+    n, e = m.num_vtx, m.idx.shape[0]
+    b = meshgen.Batch(vtx, idx, np.arange(4, dtype=np.int64) * n, np.arange(4, dtype=np.int64) * e,
+                      np.full(3, m.expected_unique), "triplicate")
+    _say("triplicate batch")
+    res = mrx.reindex_mesh_batched(*to_dev(b))
+    check_batch(b, res)
+    assert int(res.out_vtx_offsets[-1]) == 3 * m.expected_unique
+
+
+def test_empty_meshes_inside_batch():
+    import paper_2109_09812_amd as mrx
+    parts = [meshgen.batched(1, 200, 201, 0.05, 40 + s).mesh(0) for s in range(3)]
+    empty_v = np.zeros((0, 3), np.float32)
+    empty_i = np.zeros((0, 3), np.int32)
+    # meshes: [p0, empty, p1 with vertices but no elements, empty, p2]
+    vs = [parts[0].vtx, empty_v, parts[1].vtx, empty_v, parts[2].vtx]
+    is_ = [parts[0].idx, empty_i, empty_i, empty_i, parts[2].idx]
+    vo = np.concatenate([[0], np.cumsum([v.shape[0] for v in vs])]).astype(np.int64)
+    eo = np.concatenate([[0], np.cumsum([i.shape[0] for i in is_])]).astype(np.int64)
+    exp = np.array([parts[0].expected_unique, 0, 0, 0, parts[2].expected_unique])
+    b = meshgen.Batch(np.concatenate(vs), np.concatenate(is_), vo, eo, exp, "holes")
+    _say("batch with empty meshes")
+    res = mrx.reindex_mesh_batched(*to_dev(b))
+    check_batch(b, res)
+
+
+def test_batched_index_out_of_range():
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(5, 100, 1000, 0.05, 61)
+    idx = b.idx.copy()
+    # a local index equal to its own mesh's vertex count is out of range even
+    # though it is a valid id of the packed array
+    m2 = int(b.elem_offsets[2])
+    idx[m2, 0] = int(b.vtx_offsets[3] - b.vtx_offsets[2])
+    bb = meshgen.Batch(b.vtx, idx, b.vtx_offsets, b.elem_offsets, b.expected_unique, "bad")
+    _say("batch out of range")
+    with pytest.raises(IndexError):
+        mrx.reindex_mesh_batched(*to_dev(bb))
+
+
+def test_graph_replays_with_new_contents():
+    """Capture once, refill the inputs in place, replay; every replay must be
+    exact (the per-call state is cleared by a kernel inside the graph)."""
+    import paper_2109_09812_amd as mrx
+    batches = [meshgen.batched(40, 100, 8000, 0.05, 70 + s) for s in range(3)]
+    # same shapes: take the shape of the first batch and regenerate contents
+    # by permuting each mesh's vertices (indices follow), mesh sizes unchanged
+    base = batches[0]
+    rng = np.random.default_rng(5)
+    variants = [base]
+    for _ in range(2):
+        vtx = base.vtx.copy()
+        idx = base.idx.copy()
+        for m in range(base.num_meshes):
+            v0, v1 = base.vtx_offsets[m], base.vtx_offsets[m + 1]
+            e0, e1 = base.elem_offsets[m], base.elem_offsets[m + 1]
+            p = rng.permutation(v1 - v0)
+            inv = np.empty_like(p)
+            inv[p] = np.arange(p.size)
+            vtx[v0:v1] = base.vtx[v0:v1][p]
+            idx[e0:e1] = inv[base.idx[e0:e1]]
+        variants.append(meshgen.Batch(vtx, idx, base.vtx_offsets, base.elem_offsets,
+                                      base.expected_unique, "perm"))
+    tensors = to_dev(base)
+    _say("capture graph")
+    gr = mrx.GraphedBatchedReindexer(*tensors)
+    for rep, b in enumerate(variants + [variants[1]]):
+        _say("replay", rep)
+        tensors[0].copy_(torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)))
+        tensors[2].copy_(torch.from_numpy(b.idx))
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        check_batch(b, gr.result())
+        # eager work between replays
+        _ = (tensors[0].float() * 2).sum().item()

@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element, bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+from helpers import check_properties, words
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(vtx_np, idx_np):
+    v = torch.from_numpy(np.ascontiguousarray(vtx_np).view(np.int32)).to(DEV)
+    i = torch.from_numpy(np.ascontiguousarray(idx_np, dtype=np.int32)).to(DEV)
+    return v, i
+
+
+def gpu(vtx_np, idx_np, tuning=None, in_place=False):
+    import paper_2109_09812_amd as mrx
+    v, i = to_dev(vtx_np, idx_np)
+    r = mrx.reindex_mesh(v, i, tuning=tuning, in_place=in_place)
+    torch.cuda.synchronize()
+    return (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(), r.old2new.cpu().numpy(),
+            r.new2old.cpu().numpy())
+
+
+def assert_parity(vtx_np, idx_np, tuning=None, name=""):
+    _say(name, "N=%d K=%d E=%d A=%d" % (vtx_np.shape[0], words(vtx_np).shape[1] if vtx_np.size else 0,
+                                        idx_np.shape[0], idx_np.shape[1]), "tuning", tuning)
+    got = gpu(vtx_np, idx_np, tuning)
+    exp = oracle.reindex(vtx_np, idx_np)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
+        assert g.shape == e.shape, (label, g.shape, e.shape)
+        assert np.array_equal(g, e), f"{name}: {label} differs at {np.argwhere(g != e)[:5].tolist()}"
+    return got
+
+
+def test_worked_example():
+    x = np.array([1.0, 2.0, 3.0, 7.5, 4.0, 3.0, 5.0, 6.0, 8.5, 4.0], np.float32)
+    vtx = np.stack([x, np.zeros_like(x)], 1)
+    idx = np.array([[0, 1, 2], [0, 2, 4], [5, 6, 7], [5, 7, 9]], np.int32)
+    ov, oi, o2n, n2o = assert_parity(vtx, idx, name="worked example")
+    assert oi.tolist() == [[0, 1, 2], [0, 2, 3], [2, 4, 5], [2, 5, 3]]
+    assert o2n.tolist() == [0, 1, 2, -1, 3, 2, 4, 5, -1, 3]
+    assert n2o.tolist() == [0, 1, 2, 4, 6, 7]
+
+
+def test_cfg1_soup256():
+    m = meshgen.cfg1()
+    got = assert_parity(m.vtx, m.idx, name="soup256")
+    assert got[0].shape[0] == 65536
+
+
+FUZZ = [
+    # n, words, arity, distinct, used_frac, seed
+    (1, 3, 3, 1, 1.0, 1), (2, 3, 1, 2, 1.0, 2), (63, 2, 3, 20, 0.8, 3), (64, 1, 2, 64, 0.5, 4),
+    (65, 4, 4, 10, 1.0, 5), (4095, 3, 3, 900, 0.9, 6), (4096, 3, 3, 1000, 0.7, 7),
+    (4097, 3, 3, 4097, 0.6, 8), (8191, 2, 4, 3000, 0.9, 9), (8193, 5, 3, 2000, 0.9, 10),
+    (12289, 8, 4, 5000, 0.97, 11), (20000, 12, 3, 700, 0.9, 12), (30001, 16, 2, 9000, 0.8, 13),
+    (100_000, 3, 3, 30_000, 0.95, 14), (300_001, 3, 3, 60_000, 0.9, 15), (250_000, 1, 1, 1_000, 0.5, 16),
+    (150_000, 2, 4, 150_000, 1.0, 17), (99_999, 7, 3, 20_000, 0.9, 18),
+]
+
+
+@pytest.mark.parametrize("n,k,a,d,u,seed", FUZZ)
+def test_fuzz_parity(n, k, a, d, u, seed):
+    e = max(1, (n * 2) // (3 * a))
+    vtx, idx = meshgen.random_mesh(n, e, a, k, d, 7000 + seed, u)
+    assert_parity(vtx, idx, name=f"fuzz{seed}")
+
+
+def test_empty_and_degenerate():
+    import paper_2109_09812_amd as mrx
+    _say("empty mesh")
+    v, i = to_dev(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32))
+    r = mrx.reindex_mesh(v, i)
+    assert r.num_out == 0 and r.out_vtx.shape == (0, 3) and r.old2new.numel() == 0
+    # vertices but no elements: nothing is used
+    vtx = np.random.default_rng(0).random((5000, 3), dtype=np.float32)
+    got = assert_parity(vtx, np.zeros((0, 3), np.int32), name="no elements")
+    assert got[0].shape[0] == 0 and np.all(got[2] == -1)
+    # all vertices identical
+    assert_parity(np.ones((9000, 3), np.float32), np.array([[5, 8000, 17]], np.int32), name="identical")
+    # signed zeros and NaN payloads
+    w = np.array([[0x80000000], [0], [0x7FC00000], [0x7FC00001], [0x7FC00000], [0x80000000]], np.uint32)
+    got = assert_parity(w, np.arange(6, dtype=np.int32).reshape(6, 1), name="zeros/nan")
+    assert got[0].reshape(-1).tolist() == [0, 0x7FC00000, 0x7FC00001, 0x80000000]
+
+
+def test_sorted_reverse_and_single_digit_inputs():
+    n = 70_000
+    k = np.arange(n, dtype=np.uint32)
+    asc = np.stack([k // 7, k % 7, k], 1).astype(np.uint32)
+    idx = np.arange(n, dtype=np.int32).reshape(-1, 1)
+    assert_parity(asc, idx, name="ascending")
+    assert_parity(asc[::-1].copy(), idx, name="descending")
+    # keys that differ only in one byte of one word: every other digit pass sees one bucket
+    one = np.zeros((n, 3), np.uint32)
+    one[:, 1] = (np.random.default_rng(3).integers(0, 256, n).astype(np.uint32) << 16)
+    assert_parity(one, (np.arange(n, dtype=np.int32) % n).reshape(-1, 2)[: n // 2], name="one byte")
+
+
+def test_out_of_range_index_reported():
+    import paper_2109_09812_amd as mrx
+    vtx = np.random.default_rng(1).random((1000, 3), dtype=np.float32)
+    for bad in (-1, 1000, 2**31 - 1):
+        idx = np.arange(300, dtype=np.int32).reshape(100, 3)
+        idx[57, 1] = bad
+        _say("out of range", bad)
+        v, i = to_dev(vtx, idx)
+        with pytest.raises(IndexError):
+            mrx.reindex_mesh(v, i)
+    _say("no vertices, one element")
+    v, i = to_dev(np.zeros((0, 3), np.float32), np.zeros((1, 3), np.int32))
+    with pytest.raises(IndexError):
+        mrx.reindex_mesh(v, i)
+    # a later valid call on fresh outputs is unaffected
+    assert_parity(vtx, np.arange(300, dtype=np.int32).reshape(100, 3), name="after error")
+
+
+def test_in_place_remap():
+    m = meshgen.grid_soup(100, 0.05, 99, "inplace")
+    _say("in place")
+    got = gpu(m.vtx, m.idx, in_place=True)
+    exp = oracle.reindex(m.vtx, m.idx)
+    for g, e in zip(got, exp):
+        assert np.array_equal(g, e)
+
+
+def test_repeat_determinism_and_all_tunings():
+    import paper_2109_09812_amd as mrx
+    m = meshgen.grid_soup(300, 0.07, 1234, "tune")
+    exp = oracle.reindex(m.vtx, m.idx)
+    for t in mrx.tunings(12):
+        for rep in range(2):
+            _say("tuning", t.as_tuple(), "rep", rep)
+            got = gpu(m.vtx, m.idx, tuning=t)
+            for g, e in zip(got, exp):
+                assert np.array_equal(g, e)
+
+
+def test_wide_records_all_tunings():
+    import paper_2109_09812_amd as mrx
+    m = meshgen.tet_mesh(12, 0.03, 55)
+    exp = oracle.reindex(m.vtx, m.idx)
+    assert exp[0].shape[0] == 13 ** 3
+    for t in mrx.tunings(32):
+        _say("tets tuning", t.as_tuple())
+        got = gpu(m.vtx, m.idx, tuning=t)
+        for g, e in zip(got, exp):
+            assert np.array_equal(g, e)
+
+
+def test_tet_seam_does_not_merge():
+    m = meshgen.tet_mesh(16, 0.03, 77, seam=True)
+    got = assert_parity(m.vtx, m.idx, name="seam")
+    assert got[0].shape[0] == m.expected_unique
+
+
+def test_paper_quads():
+    m = meshgen.paper_quads(256)
+    got = assert_parity(m.vtx, m.idx, name="quads256")
+    assert got[0].shape[0] == 257 ** 2
+
+
+def test_cfg3_tets_full():
+    m = meshgen.cfg3()
+    got = assert_parity(m.vtx, m.idx, name="tets64")
+    assert got[0].shape[0] == 65 ** 3
+
+
+def test_cfg5_soup10m_full():
+    m = meshgen.cfg5_mesh()
+    got = assert_parity(m.vtx, m.idx, name="soup10M")
+    assert got[0].shape[0] == 1251 * 1281
+
+
+def test_cfg2_soup2048_properties():
+    """The 26.4M-vertex soup at full size, in the default launch
+    configuration: checked through properties that fix the result."""
+    m = meshgen.cfg2()
+    _say("soup2048 full size")
+    got = gpu(m.vtx, m.idx)
+    check_properties(m.vtx, m.idx, *got, expected_unique=2048 * 2048)
+    # sampled exact check: the oracle on the sub-mesh formed by the vertices of
+    # a value-closed sample (every copy of each sampled value) gives the same
+    # relative order and representatives
+    w = words(m.vtx)
+    rng = np.random.default_rng(5)
+    pick = rng.choice(got[0].shape[0], 200, replace=False)
+    sel_vals = got[0][np.sort(pick)]
+    allv = w.view(np.dtype((np.void, 12))).reshape(-1)
+    sv = np.ascontiguousarray(sel_vals).view(np.dtype((np.void, 12))).reshape(-1)
+    members = np.nonzero(np.isin(allv, sv))[0]
+    sub_vtx = m.vtx[members]
+    sub_idx = np.arange(members.size, dtype=np.int32).reshape(-1, 1)
+    sov, _, _, sn2o = oracle.reindex(sub_vtx, sub_idx)
+    assert np.array_equal(sov, sel_vals)
+    assert np.array_equal(members[sn2o], got[3][np.sort(pick)])

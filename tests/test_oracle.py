@@ -260,17 +260,18 @@ def test_all_record_widths(k):
 # ----------------------------------------------------------------- mutation check
 
 MUTANTS = {
-    "last copy represents": ("rep.emplace(key_of(vtx, i, words), (int32_t)i);",
-                             "rep[key_of(vtx, i, words)] = (int32_t)i;"),
+    "last copy represents": ("groups.emplace(key_of(vtx, i, words), Group{(int32_t)i, false, -1});",
+                             "groups[key_of(vtx, i, words)] = Group{(int32_t)i, false, -1};"),
     "signed word compare": ("using Key = std::array<uint32_t, kMaxWords>;",
                             "using Key = std::array<int32_t, kMaxWords>;"),
     "word 0 least significant": ("k[w] = vtx[i * words + w];",
                                  "k[words - 1 - w] = vtx[i * words + w];"),
-    "unused values kept": ("if (used.count(kv.first) == 0) continue;", ""),
-    "only the representative maps": ("old2new[i] = (it == new_id.end()) ? -1 : it->second;",
-                                     "old2new[i] = (it == new_id.end() || new2old[it->second] != (int32_t)i)"
-                                     " ? -1 : it->second;"),
+    "unused values kept": ("if (!g.used) continue;", ""),
+    "only the representative maps": ("old2new[i] = groups.at(key_of(vtx, i, words)).new_id;",
+                                     "old2new[i] = groups.at(key_of(vtx, i, words)).rep == (int32_t)i"
+                                     " ? groups.at(key_of(vtx, i, words)).new_id : -1;"),
     "index bound off by one": ("idx[k] >= num_vtx", "idx[k] > num_vtx"),
+    "new ids off by one": ("g.new_id = (int32_t)u;", "g.new_id = (int32_t)u + (u > 0);"),
 }
 
 
