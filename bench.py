@@ -252,6 +252,27 @@ def cpu_baseline(meshgen):
                       f"({sample.num_vtx} vertices, 5% unused)"}
 
 
+def kernels_only(args, torch, mrx, meshgen):
+    """Profiler target: W + K re-index steps of the timed workload, then a
+    plain device copy of 1 GiB (torch copy_) three times, whose counter
+    readings calibrate the byte counters against a known size."""
+    m = meshgen.cfg2()
+    dev = torch.device("cuda:0")
+    vtx = torch.from_numpy(m.vtx.view("int32")).to(dev)
+    idx = torch.from_numpy(m.idx).to(dev)
+    rx = mrx.Reindexer(vtx, idx, tuning=args.tuning)
+    for _ in range(args.warmup + args.steps):
+        rx.launch()
+    torch.cuda.synchronize()
+    a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(7)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernels", "steps": args.steps, "warmup": args.warmup,
+                      "copy_probe_bytes_each_way": a.numel() * 4, "unique_out": rx.result().num_out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +282,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gather", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", choices=("full", "kernels"), default="full",
+                    help="kernels: only the timed re-index steps and a 1 GiB copy probe (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -275,6 +298,9 @@ def main():
     mrx.load()
     assert torch.cuda.is_available(), "no GPU visible"
 
+    if args.mode == "kernels":
+        kernels_only(args, torch, mrx, meshgen)
+        return
     single = bench_single(args, torch, mrx, meshgen)
     extras = {}
     if not args.no_gather:

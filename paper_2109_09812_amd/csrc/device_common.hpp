@@ -173,15 +173,6 @@ __device__ __forceinline__ void store_words(uint32_t* __restrict__ p, const uint
   }
 }
 
-// Word `i` of a register array, `i` wave-uniform (a select chain, no scratch).
-template <int N>
-__device__ __forceinline__ uint32_t pick_word(const uint32_t (&v)[N], int i) {
-  uint32_t r = v[0];
-#pragma unroll
-  for (int w = 1; w < N; ++w) r = (i == w) ? v[w] : r;
-  return r;
-}
-
 // Mesh id of global vertex id `id` in a packed batch: the b with
 // off[b] <= id < off[b+1] (binary search; off has nmesh+1 entries).
 __device__ __forceinline__ uint32_t mesh_of(const int64_t* __restrict__ off, int32_t nmesh,

@@ -202,6 +202,19 @@ int64_t grid_for(int64_t work, int block, int64_t cap = 8192) {
   return std::max<int64_t>(1, std::min<int64_t>((work + block - 1) / block, cap));
 }
 
+// Digit location of LSD key bit `bit` (0 = least significant bit of the last
+// word): word masks select the word holding it and the next more
+// significant word.
+void set_digit(SortPassArgs& a, int K, int bit) {
+  const int lo = K - 1 - bit / 32;
+  const int hi = lo - 1;
+  for (int w = 0; w < 16; ++w) {
+    a.lo_mask[w] = (w == lo) ? 0xFFFFFFFFu : 0u;
+    a.hi_mask[w] = (w == hi) ? 0xFFFFFFFFu : 0u;
+  }
+  a.shift = bit % 32;
+}
+
 mrx_status check_launch() {
   return hipGetLastError() == hipSuccess ? MRX_OK : MRX_ERR_HIP;
 }
@@ -384,10 +397,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
       a.ctl = ctl;
       a.status = status;
       a.n = n;
-      const int bit = p * v.D;
-      a.word_lo = K - 1 - bit / 32;
-      a.word_hi = a.word_lo - 1;
-      a.shift = bit % 32;
+      set_digit(a, K, p * v.D);
       a.tag = uint32_t(p + 1);
       prof_mark(p == 0 ? "onesweep_first" : "onesweep", s);
       v.pass(a, p == 0 ? kPassFirst : kPassKey, L.tiles_sort, s);
@@ -522,14 +532,9 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
       a.tag = uint32_t(p + 1);
       int mode = kPassKey;
       if (p < L.P_key) {
-        const int bit = p * v.D;
-        a.word_lo = K - 1 - bit / 32;
-        a.word_hi = a.word_lo - 1;
-        a.shift = bit % 32;
+        set_digit(a, K, p * v.D);
         if (p == 0) mode = kPassFirst;
       } else {
-        a.word_lo = 0;
-        a.word_hi = -1;
         a.shift = (p - L.P_key) * v.D;
         mode = kPassMesh;
       }

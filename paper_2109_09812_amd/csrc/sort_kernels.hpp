@@ -25,12 +25,32 @@ struct SortPassArgs {
   int32_t* status;
   const int64_t* mesh_off;      // mesh passes: [nmesh+1] vertex offsets
   int32_t nmesh;
-  int32_t word_lo;              // key word holding the digit's low bits
-  int32_t word_hi;              // next more significant word (-1: none)
+  // The digit is bits [shift, shift + D) of (word_hi:word_lo). The words are
+  // selected with per-word masks (all-ones for the chosen word, zero for the
+  // others) rather than an index, so element words stay in registers.
+  uint32_t lo_mask[16];
+  uint32_t hi_mask[16];
   int32_t shift;                // bit offset of the digit inside word_lo (mesh passes: inside the mesh id)
   int64_t n;
   uint32_t tag;
 };
+
+// (word_hi:word_lo) >> shift, masked to D bits, with the words chosen by masks.
+template <int D, int K, int N>
+__device__ __forceinline__ uint32_t masked_digit(const uint32_t (&v)[N], const uint32_t* lo_mask,
+                                                 const uint32_t* hi_mask, int shift) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (int w = 0; w < K; ++w) lo |= v[w] & lo_mask[w];
+  uint32_t x = lo >> shift;
+  if constexpr (32 % D != 0) {
+    uint32_t hi = 0;
+#pragma unroll
+    for (int w = 0; w < K; ++w) hi |= v[w] & hi_mask[w];
+    if (shift + D > 32) x |= hi << (32 - shift);  // digit spans two words
+  }
+  return x & ((1u << D) - 1u);
+}
 
 template <int D>
 __device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift) {
@@ -200,9 +220,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu)) : 0u;
       dig[j] = (m >> a.shift) & MASK;
     } else {
-      const uint32_t lo = pick_word<S>(v[j], a.word_lo);
-      const uint32_t hi = (32 % D != 0 && a.word_hi >= 0) ? pick_word<S>(v[j], a.word_hi) : 0u;
-      dig[j] = digit_of<D>(lo, hi, a.shift);
+      dig[j] = masked_digit<D, K>(v[j], a.lo_mask, a.hi_mask, a.shift);
     }
   }
 
@@ -301,7 +319,15 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // ---- scatter: consecutive q of one digit go to consecutive addresses
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
-    if (int64_t(opos[r]) < n) store_words<S>(a.dst + int64_t(opos[r]) * S, v[r]);
+    if (int64_t(opos[r]) < n) {
+#ifdef MRX_SCATTER_NT
+      uint32_t* d = a.dst + int64_t(opos[r]) * S;
+#pragma unroll
+      for (int w = 0; w < S; ++w) __builtin_nontemporal_store(v[r][w], d + w);
+#else
+      store_words<S>(a.dst + int64_t(opos[r]) * S, v[r]);
+#endif
+    }
   }
 }
 
