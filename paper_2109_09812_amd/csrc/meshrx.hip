@@ -28,20 +28,18 @@ __global__ void k_fill_zero(uint4* __restrict__ p, int64_t n16, int32_t* status,
 
 // Batch epilogue: out_off[b] = number of used groups of meshes < b, read
 // from cmap at the first sorted position of mesh b (a head, since heads
-// break at mesh starts); new2old made mesh-local.
+// break at mesh starts).
 __global__ void k_batch_offsets(const int64_t* __restrict__ vtx_off, int32_t nmesh,
-                                const uint32_t* __restrict__ sorted, int32_t S,
-                                const int32_t* __restrict__ o2g, const int32_t* __restrict__ cmap,
+                                const uint2* __restrict__ pairs, const int32_t* __restrict__ cmap,
                                 const Control* ctl, const int64_t* __restrict__ total_used,
                                 int64_t n, int64_t* __restrict__ out_off) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nmesh) return;
   const int64_t p = vtx_off[b];
   int64_t r = *total_used;
-  if (b < nmesh && p < n) {
-    const uint32_t org = sorted[p * S + (S - 1)] & 0x7FFFFFFFu;
-    const int32_t g = org < n ? o2g[org] : -1;
-    if (g >= 0 && g < ctl->num_groups) {
+  if (b < nmesh && p >= 0 && p < n) {
+    const uint32_t g = pairs[p].x;
+    if (int64_t(g) < ctl->num_groups) {
       const int32_t c = cmap[g];
       r = c >= 0 ? c : ~c;
     }
@@ -144,7 +142,7 @@ struct Layout {
   // zeroed region
   size_t ctl = 0, counters = 0, hist = 0, lookback = 0, used_v = 0, used_g = 0, zero_end = 0;
   // scratch
-  size_t buf_a = 0, buf_b = 0, o2g = 0, uniq = 0, rep = 0, cmap = 0, total = 0;
+  size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, total = 0;
 };
 
 Layout make_layout(int64_t n, int K, int32_t nmesh, const SortVariant& v) {
@@ -167,7 +165,6 @@ Layout make_layout(int64_t n, int K, int32_t nmesh, const SortVariant& v) {
   L.zero_end = off;
   L.buf_a = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
-  L.o2g = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
   L.rep = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
   L.cmap = off;     off = align_up(off + sizeof(int32_t) * size_t(n));
@@ -213,6 +210,10 @@ void set_digit(SortPassArgs& a, int K, int bit) {
     a.hi_mask[w] = (w == hi) ? 0xFFFFFFFFu : 0u;
   }
   a.shift = bit % 32;
+}
+
+int64_t rand_grid(int64_t work) {
+  return std::max<int64_t>(1, (work + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems));
 }
 
 mrx_status check_launch() {
@@ -362,7 +363,6 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
   uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
   uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
-  int32_t* o2g = reinterpret_cast<int32_t*>(ws + L.o2g);
   uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
   int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
@@ -375,7 +375,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
   // Step 1: mark referenced vertices (and report out-of-range entries)
   if (m > 0) {
     prof_mark("mark_used", s);
-    hipLaunchKernelGGL((k_mark_used<false>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+    hipLaunchKernelGGL((k_mark_used<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
                        nullptr, nullptr, 0, used_v, status);
   }
   if (n > 0) {
@@ -408,7 +408,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     FlagScanArgs f{};
     f.sorted = src;
     f.n = n;
-    f.o2g = o2g;
+    f.pairs = reinterpret_cast<uint2*>(buf[cur]);  // the buffer the last pass read from
     f.uniq = uniq;
     f.rep = rep;
     f.used_g = used_g;
@@ -438,13 +438,13 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     prof_mark("compact", s);
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("old2new", s);
-    hipLaunchKernelGGL((k_old2new<false>), dim3(grid_for(n, 256)), dim3(256), 0, s, o2g, cmap, n, n,
-                       nullptr, nullptr, 0, old2new);
+    hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n)), dim3(kRandBlock), 0, s,
+                       f.pairs, cmap, n, nullptr, nullptr, 0, old2new);
   }
   // Step 4: remap the index array
   if (m > 0) {
     prof_mark("remap", s);
-    hipLaunchKernelGGL((k_remap<false>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+    hipLaunchKernelGGL((k_remap<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
                        nullptr, nullptr, 0, old2new, out_idx);
   }
   prof_mark(nullptr, s);
@@ -491,7 +491,6 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
   uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
   uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
-  int32_t* o2g = reinterpret_cast<int32_t*>(ws + L.o2g);
   uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
   int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
@@ -504,7 +503,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
                      static_cast<int64_t*>(nullptr));
   if (m > 0) {
     prof_mark("mark_used", s);
-    hipLaunchKernelGGL((k_mark_used<true>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+    hipLaunchKernelGGL((k_mark_used<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
                        vtx_offsets, elem_offsets, num_meshes, used_v, status);
   }
   if (n > 0) {
@@ -546,7 +545,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     FlagScanArgs f{};
     f.sorted = src;
     f.n = n;
-    f.o2g = o2g;
+    f.pairs = reinterpret_cast<uint2*>(buf[cur]);  // the buffer the last pass read from
     f.uniq = uniq;
     f.rep = rep;
     f.used_g = used_g;
@@ -578,11 +577,12 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("batch_offsets", s);
     hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets,
-                       num_meshes, static_cast<const uint32_t*>(src), int32_t(L.S), o2g, cmap, ctl,
-                       &ctl->num_used, n, out_vtx_offsets);
+                       num_meshes, static_cast<const uint2*>(f.pairs), static_cast<const int32_t*>(cmap),
+                       static_cast<const Control*>(ctl), static_cast<const int64_t*>(&ctl->num_used), n,
+                       out_vtx_offsets);
     prof_mark("old2new", s);
-    hipLaunchKernelGGL((k_old2new<true>), dim3(grid_for(n, 256)), dim3(256), 0, s, o2g, cmap, n, n,
-                       vtx_offsets, out_vtx_offsets, num_meshes, old2new);
+    hipLaunchKernelGGL((k_scatter_old2new<true>), dim3(rand_grid(n)), dim3(kRandBlock), 0, s,
+                       f.pairs, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes, old2new);
     if (new2old) {
       prof_mark("localize_new2old", s);
       hipLaunchKernelGGL(k_localize_new2old, dim3(grid_for(n, 256)), dim3(256), 0, s, new2old,
@@ -591,12 +591,13 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   } else {
     prof_mark("batch_offsets", s);
     hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets,
-                       num_meshes, static_cast<const uint32_t*>(nullptr), int32_t(L.S), o2g, cmap, ctl,
-                       &ctl->num_used, n, out_vtx_offsets);
+                       num_meshes, static_cast<const uint2*>(nullptr), static_cast<const int32_t*>(cmap),
+                       static_cast<const Control*>(ctl), static_cast<const int64_t*>(&ctl->num_used), n,
+                       out_vtx_offsets);
   }
   if (m > 0) {
     prof_mark("remap", s);
-    hipLaunchKernelGGL((k_remap<true>), dim3(grid_for(m, 256)), dim3(256), 0, s, idx, m, arity, n,
+    hipLaunchKernelGGL((k_remap<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
                        vtx_offsets, elem_offsets, num_meshes, old2new, out_idx);
   }
   prof_mark(nullptr, s);

@@ -10,40 +10,57 @@ namespace mrx {
 constexpr int32_t kErrIndex = 3;     // MRX_ERR_INDEX_OUT_OF_RANGE
 constexpr int32_t kErrInternal = 7;  // MRX_ERR_INTERNAL
 
+// Random-access kernels handle kRandItems independent elements per thread:
+// all loads are issued before any dependent access, so each wave keeps
+// several random requests in flight.
+constexpr int kRandItems = 4;
+constexpr int kRandBlock = 256;
+
 // Step 1: used[v] = 1 for every referenced vertex v. Batched meshes carry
 // mesh-local indices; the element's mesh supplies the vertex offset.
 template <bool BATCHED>
-__global__ void k_mark_used(const int32_t* __restrict__ idx, int64_t m, int32_t arity, int64_t n,
-                            const int64_t* __restrict__ vtx_off, const int64_t* __restrict__ elem_off,
-                            int32_t nmesh, uint8_t* __restrict__ used, int32_t* status) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < m; k += stride) {
-    const int32_t v = idx[k];
+__global__ __launch_bounds__(kRandBlock) void k_mark_used(const int32_t* __restrict__ idx, int64_t m,
+                                                          int32_t arity, int64_t n,
+                                                          const int64_t* __restrict__ vtx_off,
+                                                          const int64_t* __restrict__ elem_off,
+                                                          int32_t nmesh, uint8_t* __restrict__ used,
+                                                          int32_t* status) {
+  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
+  int32_t v[kRandItems];
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) {
+    const int64_t k = base + it * kRandBlock;
+    v[it] = k < m ? stream_load(idx + k) : 0;
+  }
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) {
+    const int64_t k = base + it * kRandBlock;
+    if (k >= m) break;
     int64_t lo = 0, cnt = n;
     if constexpr (BATCHED) {
       const uint32_t b = mesh_of(elem_off, nmesh, k / arity);
       lo = vtx_off[b];
       cnt = vtx_off[b + 1] - lo;
     }
-    if (v < 0 || v >= cnt || lo < 0 || lo + v >= n) {
+    if (v[it] < 0 || v[it] >= cnt || lo < 0 || lo + v[it] >= n) {
       atomicMax(status, kErrIndex);
     } else {
-      used[lo + v] = 1;
+      used[lo + v[it]] = 1;
     }
   }
 }
 
 // ----------------------------------------------------------------------------
-// Step 2 (flags and prefix sum) fused with the scatters of Steps 3 and 4.
+// Step 2 (flags and prefix sum) fused with the scatter of Step 3.
 // Over the sorted elements: head(i) = i == 0 || key(i) != key(i-1) (or, for a
 // batch, i starts a mesh); gid(i) = inclusive_sum(head)(i) - 1. Heads write
-// the group's record and representative id; every element writes its
-// group id to the old -> group map and marks the group used if the vertex is
-// referenced. The last tile stores G.
+// the group's record and representative id; every element writes the pair
+// (gid(i), original id) at its sorted position and marks the group used if
+// the vertex is referenced. The last tile stores G.
 struct FlagScanArgs {
   const uint32_t* sorted;  // [n][K+1]
   int64_t n;
-  int32_t* o2g;            // [n] original id -> group id
+  uint2* pairs;            // [n] (group id, original id) in sorted order
   uint32_t* uniq;          // [G][K] group records
   int32_t* rep;            // [G] smallest original id of the group
   uint8_t* used_g;         // [G] zeroed; 1 = some copy referenced
@@ -74,23 +91,36 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
   uint32_t incl[IPT];   // heads at or before this element within the wave's (j, lane) order
   bool head[IPT];
   uint32_t running = 0;
+  // The element before this wave's first one (positions are consecutive
+  // within the wave: item j, lane l is wave_base + 64 j + l).
+  uint32_t carry[K];
+  {
+    const int64_t p0 = wave_base - lane - 1;
+#pragma unroll
+    for (int w = 0; w < K; ++w) carry[w] = (p0 >= 0 && p0 < n) ? a.sorted[p0 * S + w] : 0u;
+  }
+  uint32_t e[IPT][S];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t pos = wave_base + j * kWave;
+    if (pos < n) load_words<S>(a.sorted + pos * S, e[j]);
+    else {
+#pragma unroll
+      for (int w = 0; w < S; ++w) e[j][w] = 0;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int64_t pos = wave_base + j * kWave;
     const bool valid = pos < n;
-    uint32_t e[S];
-    if (valid) load_words<S>(a.sorted + pos * S, e);
-    else {
-#pragma unroll
-      for (int w = 0; w < S; ++w) e[w] = 0;
-    }
     bool h = false;
     bool differs = false;
 #pragma unroll
     for (int w = 0; w < K; ++w) {
-      uint32_t pw = __shfl_up(e[w], 1, kWave);
-      if (lane == 0 && valid && pos > 0) pw = a.sorted[(pos - 1) * S + w];
-      differs |= (pw != e[w]);
+      uint32_t pw = __shfl_up(e[j][w], 1, kWave);
+      if (lane == 0) pw = carry[w];
+      carry[w] = __shfl(e[j][w], kWave - 1, kWave);  // predecessor of lane 0 at item j + 1
+      differs |= (pw != e[j][w]);
     }
     if (valid) {
       h = (pos == 0) || differs;
@@ -99,7 +129,7 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
         h = h || (a.mesh_off[b] == pos);
       }
     }
-    id[j] = e[K];
+    id[j] = e[j][K];
     const uint64_t hm = ballot(h);
     incl[j] = running + uint32_t(popc64(hm & lanemask_lt())) + (h ? 1u : 0u);
     running += uint32_t(popc64(hm));
@@ -141,13 +171,13 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
       atomicMax(a.status, kErrInternal);
       continue;
     }
-    if (head[j]) {  // the record was loaded before the look-back; this re-read hits the cache
+    if (head[j]) {
 #pragma unroll
-      for (int w = 0; w < K; ++w) a.uniq[int64_t(g) * K + w] = a.sorted[pos * S + w];
+      for (int w = 0; w < K; ++w) a.uniq[int64_t(g) * K + w] = e[j][w];
       a.rep[g] = int32_t(org);
     }
     if (id[j] & 0x80000000u) a.used_g[g] = 1;
-    a.o2g[org] = int32_t(g);
+    a.pairs[pos] = make_uint2(g, org);
     if (pos == n - 1) a.ctl->num_groups = int64_t(g) + 1;
   }
 }
@@ -242,40 +272,73 @@ __global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
   }
 }
 
-// old2new[i] = new id of vertex i's group, -1 if unused. For a batch the
-// global new id is made mesh-local with the mesh's output offset.
+// Step 4's map: old2new[org] = new id of the group of each sorted element
+// (-1 if the group is unused), a scatter from sorted positions; the cmap
+// reads follow the non-decreasing group ids. For a batch the new id is made
+// mesh-local with the mesh's output offset.
 template <bool BATCHED>
-__global__ void k_old2new(const int32_t* __restrict__ o2g, const int32_t* __restrict__ cmap, int64_t n,
-                          int64_t num_groups_cap, const int64_t* __restrict__ vtx_off,
-                          const int64_t* __restrict__ out_off, int32_t nmesh,
-                          int32_t* __restrict__ old2new) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int32_t g = o2g[i];
-    int32_t c = (g >= 0 && g < num_groups_cap) ? cmap[g] : -1;
-    if (c < 0) c = -1;
-    if constexpr (BATCHED) {
-      if (c >= 0) c -= int32_t(out_off[mesh_of(vtx_off, nmesh, i)]);
+__global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __restrict__ pairs,
+                                                                const int32_t* __restrict__ cmap, int64_t n,
+                                                                const int64_t* __restrict__ vtx_off,
+                                                                const int64_t* __restrict__ out_off,
+                                                                int32_t nmesh, int32_t* __restrict__ old2new) {
+  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
+  uint2 p[kRandItems];
+  int32_t c[kRandItems];
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) {
+    const int64_t i = base + it * kRandBlock;
+    if (i < n) {
+      p[it].x = stream_load(&pairs[i].x);
+      p[it].y = stream_load(&pairs[i].y);
+    } else {
+      p[it] = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
     }
-    old2new[i] = c;
+  }
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it)
+    c[it] = (int64_t(p[it].x) < n && int64_t(p[it].y) < n) ? cmap[p[it].x] : -1;
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) {
+    if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) continue;  // past the end (or a failed wait)
+    int32_t cc = c[it] < 0 ? -1 : c[it];
+    if constexpr (BATCHED) {
+      if (cc >= 0) cc -= int32_t(out_off[mesh_of(vtx_off, nmesh, int64_t(p[it].y))]);
+    }
+    old2new[p[it].y] = cc;
   }
 }
 
 // Step 4: out_idx[k] = old2new[idx[k]] (-1 for an out-of-range entry).
 template <bool BATCHED>
-__global__ void k_remap(const int32_t* idx, int64_t m, int32_t arity, int64_t n,
-                        const int64_t* __restrict__ vtx_off, const int64_t* __restrict__ elem_off,
-                        int32_t nmesh, const int32_t* __restrict__ old2new, int32_t* out_idx) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < m; k += stride) {
-    const int32_t v = idx[k];
-    int64_t lo = 0, cnt = n;
-    if constexpr (BATCHED) {
-      const uint32_t b = mesh_of(elem_off, nmesh, k / arity);
-      lo = vtx_off[b];
-      cnt = vtx_off[b + 1] - lo;
+__global__ __launch_bounds__(kRandBlock) void k_remap(const int32_t* idx, int64_t m, int32_t arity, int64_t n,
+                                                      const int64_t* __restrict__ vtx_off,
+                                                      const int64_t* __restrict__ elem_off, int32_t nmesh,
+                                                      const int32_t* __restrict__ old2new, int32_t* out_idx) {
+  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
+  int64_t src[kRandItems];
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) {
+    const int64_t k = base + it * kRandBlock;
+    src[it] = -1;
+    if (k < m) {
+      const int32_t v = stream_load(idx + k);
+      int64_t lo = 0, cnt = n;
+      if constexpr (BATCHED) {
+        const uint32_t b = mesh_of(elem_off, nmesh, k / arity);
+        lo = vtx_off[b];
+        cnt = vtx_off[b + 1] - lo;
+      }
+      if (v >= 0 && v < cnt && lo >= 0 && lo + v < n) src[it] = lo + v;
     }
-    out_idx[k] = (v >= 0 && v < cnt && lo >= 0 && lo + v < n) ? old2new[lo + v] : -1;
+  }
+  int32_t r[kRandItems];
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) r[it] = src[it] >= 0 ? old2new[src[it]] : -1;
+#pragma unroll
+  for (int it = 0; it < kRandItems; ++it) {
+    const int64_t k = base + it * kRandBlock;
+    if (k < m) stream_store(out_idx + k, r[it]);
   }
 }
 

@@ -1,5 +1,7 @@
 // Instantiates the sort and flag-scan kernels for one record width.
 // Built once per K with -DMRX_INST_K=<K>.
+#include <algorithm>
+
 #include "registry.hpp"
 
 #ifndef MRX_INST_K
@@ -32,9 +34,11 @@ void launch_pass(const SortPassArgs& a, int mode, int64_t grid, hipStream_t s) {
 
 template <int D>
 void launch_hist(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) {
-  constexpr int B = 256, ITEMS = 16;
-  const int64_t grid = (n + B * ITEMS - 1) / (B * ITEMS);
-  if (grid > 0) hipLaunchKernelGGL((k_histogram<K, D, B, ITEMS>), dim3(grid), dim3(B), 0, s, vtx, n, hist);
+  constexpr int B = 256, GROUPS = 4;
+  constexpr int R = 4 / gcd4(K);
+  const int64_t per_block = int64_t(B) * GROUPS * R;
+  const int64_t grid = (n + per_block - 1) / per_block;
+  if (grid > 0) hipLaunchKernelGGL((k_histogram<K, D, B, GROUPS>), dim3(grid), dim3(B), 0, s, vtx, n, hist);
 }
 
 template <int D>
@@ -80,6 +84,7 @@ void MRX_CAT(register_k, MRX_INST_K)(std::vector<SortVariant>& out) {
   out.push_back(make<8, 512, 16>());
   out.push_back(make<8, 256, 12>());
   out.push_back(make<8, 512, 8>());
+  out.push_back(make<8, 1024, 8>());
 #elif MRX_INST_K == 8
   out.push_back(make<8, 512, 8>());
   out.push_back(make<8, 256, 6>());

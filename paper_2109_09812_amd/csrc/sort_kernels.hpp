@@ -64,11 +64,41 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift
 // ----------------------------------------------------------------------------
 // Digit histograms of every key pass in one read of the records.
 // hist[p * RADIX + b] += number of records whose pass-p digit is b.
-template <int K, int D, int BLOCK, int ITEMS>
+//
+// Records are read in groups of R = 4 / gcd(K, 4) consecutive records, i.e.
+// R*K words = a whole number of 16-byte vectors, so a wave reads one
+// contiguous stretch per load instruction (when the records are 16-byte
+// aligned; otherwise word by word).
+constexpr int gcd4(int k) { return (k % 4 == 0) ? 4 : (k % 2 == 0) ? 2 : 1; }
+
+template <int K, int D>
+__device__ __forceinline__ void hist_record(const uint32_t* w, uint32_t* s_h, uint32_t* last,
+                                            uint32_t* run) {
+  constexpr int RADIX = 1 << D;
+  constexpr int P = (32 * K + D - 1) / D;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int bit = p * D;
+    const int wi = K - 1 - bit / 32;
+    const int hi = wi - 1;
+    const uint32_t d = digit_of<D>(w[wi], hi >= 0 ? w[hi >= 0 ? hi : 0] : 0u, bit % 32);
+    if (run[p] != 0 && d == last[p]) {
+      ++run[p];
+    } else {
+      if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
+      last[p] = d;
+      run[p] = 1;
+    }
+  }
+}
+
+template <int K, int D, int BLOCK, int GROUPS>
 __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t* __restrict__ vtx, int64_t n,
                                                      uint32_t* __restrict__ hist) {
   constexpr int RADIX = 1 << D;
   constexpr int P = (32 * K + D - 1) / D;
+  constexpr int R = 4 / gcd4(K);   // records per group
+  constexpr int GW = R * K;        // words per group (multiple of 4)
   __shared__ uint32_t s_h[P * RADIX];
   for (int i = threadIdx.x; i < P * RADIX; i += BLOCK) s_h[i] = 0;
   __syncthreads();
@@ -80,27 +110,31 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t* __restrict_
 #pragma unroll
   for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
 
-  const int64_t base = int64_t(blockIdx.x) * (BLOCK * ITEMS);
-  for (int it = 0; it < ITEMS; ++it) {
-    const int64_t pos = base + int64_t(it) * BLOCK + threadIdx.x;
-    if (pos >= n) break;
-    uint32_t w[K];
+  // Grid-stride over chunks of BLOCK * GROUPS groups: few blocks, so few
+  // global atomics on the (shared, contended) histogram words.
+  const bool vec = (reinterpret_cast<uintptr_t>(vtx) & 15) == 0;
+  const int64_t groups = (n + R - 1) / R;
+  for (int64_t g0 = int64_t(blockIdx.x) * (BLOCK * GROUPS); g0 < groups;
+       g0 += int64_t(gridDim.x) * (BLOCK * GROUPS))
+  for (int it = 0; it < GROUPS; ++it) {
+    const int64_t g = g0 + int64_t(it) * BLOCK + threadIdx.x;
+    const int64_t r0 = g * R;
+    if (r0 >= n) break;
+    uint32_t w[GW];
+    if (vec && r0 + R <= n) {
+      const uint4* p4 = reinterpret_cast<const uint4*>(vtx + r0 * K);
 #pragma unroll
-    for (int k = 0; k < K; ++k) w[k] = vtx[pos * K + k];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int bit = p * D;
-      const int wi = K - 1 - bit / 32;
-      const int hi = wi - 1;
-      const uint32_t d = digit_of<D>(w[wi], hi >= 0 ? w[hi >= 0 ? hi : 0] : 0u, bit % 32);
-      if (run[p] != 0 && d == last[p]) {
-        ++run[p];
-      } else {
-        if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
-        last[p] = d;
-        run[p] = 1;
+      for (int q = 0; q < GW / 4; ++q) {
+        const uint4 x = p4[q];
+        w[4 * q] = x.x; w[4 * q + 1] = x.y; w[4 * q + 2] = x.z; w[4 * q + 3] = x.w;
       }
+    } else {
+#pragma unroll
+      for (int q = 0; q < GW; ++q) w[q] = (r0 * K + q < n * K) ? vtx[r0 * K + q] : 0u;
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r0 + r < n) hist_record<K, D>(w + r * K, s_h, last, run);
   }
 #pragma unroll
   for (int p = 0; p < P; ++p)
@@ -174,10 +208,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   constexpr int BPT = (RADIX + BLOCK - 1) / BLOCK;
   static_assert(D <= 16, "digits are staged as 16-bit values");
 
+  // Word planes go through LDS double-buffered when two planes fit next to
+  // the rest; big tiles use one plane and an extra barrier per word.
+  constexpr int NBUF = (2 * TILE * 4 + TILE * 2 + WAVES * RADIX * 4 <= 64 * 1024) ? 2 : 1;
   __shared__ uint32_t s_hist[WAVES * RADIX];
   __shared__ uint32_t s_start[RADIX];
   __shared__ uint32_t s_base[RADIX];
-  __shared__ uint32_t s_buf[2][TILE];
+  __shared__ uint32_t s_buf[NBUF][TILE];
   __shared__ uint16_t s_dig[TILE];
   __shared__ uint32_t s_wave[WAVES];
   __shared__ uint32_t s_tile;
@@ -304,7 +341,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // ---- reorder one word plane at a time through LDS (double-buffered)
 #pragma unroll
   for (int w = 0; w < S; ++w) {
-    uint32_t* buf = s_buf[w & 1];
+    uint32_t* buf = s_buf[w % NBUF];
+    if (NBUF == 1 && w > 0) __syncthreads();  // previous plane fully read
 #pragma unroll
     for (int j = 0; j < IPT; ++j)
       if ((wave_base + j * kWave) < n) buf[rank[j]] = v[j][w];
