@@ -27,6 +27,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "onesweep_soup2048_traffic.json")
+# sources that define the measured LSD pass kernel
+PASS_SOURCES = ("paper_2109_09812_amd/csrc/sort_kernels.hpp", "paper_2109_09812_amd/csrc/device_common.hpp",
+                "paper_2109_09812_amd/csrc/sort_inst.hip", "paper_2109_09812_amd/csrc/registry.hpp")
+
+
+def pass_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in PASS_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per LSD pass launch from the committed rocprofv3 counter
+    summary, or None if the pass kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != pass_sources_sha():
+        return None
+    return int(t["read_bytes_per_launch"] + t["write_bytes_per_launch"])
 
 
 def log(*a):
@@ -66,6 +92,18 @@ def kernel_table(records):
     return {k: (c, t / c) for k, (c, t) in agg.items()}
 
 
+def choose_tuning(args, vtx, idx):
+    """--tuning if given, else the autotuner's pick (cached per workload shape)."""
+    tuning = args.tuning
+    if tuning is None:
+        from paper_2109_09812_amd import autotune
+        t, report = autotune.autotune(vtx, idx, reps=3)
+        tuning = t.as_tuple()
+        log(f"autotuned: {tuning} from {report}")
+    args.chosen_tuning = tuning
+    return tuning
+
+
 def bench_single(args, torch, mrx, meshgen):
     m = meshgen.cfg2()
     n, k = m.vtx.shape
@@ -74,7 +112,8 @@ def bench_single(args, torch, mrx, meshgen):
     dev = torch.device("cuda:0")
     vtx = torch.from_numpy(m.vtx.view("int32")).to(dev)
     idx = torch.from_numpy(m.idx).to(dev)
-    rx = mrx.Reindexer(vtx, idx, tuning=args.tuning)
+    tuning = choose_tuning(args, vtx, idx)
+    rx = mrx.Reindexer(vtx, idx, tuning=tuning)
     log(f"soup2048: N={n} E={e} K={k}; warmup {args.warmup}")
     for _ in range(args.warmup):
         rx.launch()
@@ -131,8 +170,10 @@ def bench_batched(args, torch, mrx, meshgen):
     vo = torch.from_numpy(b.vtx_offsets).to(dev)
     idx = torch.from_numpy(b.idx).to(dev)
     eo = torch.from_numpy(b.elem_offsets).to(dev)
-    log(f"batch4096: N={n} meshes={b.num_meshes}; capturing graph")
-    g = mrx.GraphedBatchedReindexer(vtx, vo, idx, eo)
+    from paper_2109_09812_amd import autotune
+    t, report = autotune.autotune(vtx, idx, vo, eo, reps=2)
+    log(f"batch4096: N={n} meshes={b.num_meshes}; autotuned {t.as_tuple()} from {report}; capturing graph")
+    g = mrx.GraphedBatchedReindexer(vtx, vo, idx, eo, tuning=t)
     g.replay()
     torch.cuda.synchronize()
     reps = max(1, min(args.steps, 5))
@@ -183,6 +224,7 @@ def bench_batched(args, torch, mrx, meshgen):
             "total_vertices": n, "batched_ms": round(ms_b, 3), "per_mesh_ms": round(ms_p, 3),
             "batched_vertices_per_s": n / (ms_b * 1e-3), "per_mesh_vertices_per_s": n / (ms_p * 1e-3),
             "speedup": round(ms_p / ms_b, 2), "batched_equals_per_mesh": bool(same),
+            "tuning": list(t.as_tuple()),
             "closed_form_counts_ok": exp_ok}
 
 
@@ -260,7 +302,8 @@ def kernels_only(args, torch, mrx, meshgen):
     dev = torch.device("cuda:0")
     vtx = torch.from_numpy(m.vtx.view("int32")).to(dev)
     idx = torch.from_numpy(m.idx).to(dev)
-    rx = mrx.Reindexer(vtx, idx, tuning=args.tuning)
+    rx = mrx.Reindexer(vtx, idx, tuning=choose_tuning(args, vtx, idx))
+    torch.cuda.synchronize()
     for _ in range(args.warmup + args.steps):
         rx.launch()
     torch.cuda.synchronize()
@@ -270,6 +313,7 @@ def kernels_only(args, torch, mrx, meshgen):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "steps": args.steps, "warmup": args.warmup,
+                      "tuning": list(args.chosen_tuning),
                       "copy_probe_bytes_each_way": a.numel() * 4, "unique_out": rx.result().num_out}))
 
 
@@ -333,12 +377,13 @@ def main():
         "config": {"workload": "soup2048: triangle soup of a 2048x2048 grid, 26,398,316 fp32 xyz vertices "
                                "(25,141,254 referenced + 5% unused), 8,380,418 int32 triangles, permuted",
                    "num_vertices": n, "num_indices": single["m"], "unique_out": single["u"],
-                   "record_bytes": single["r_bytes"], "tuning": args.tuning or "default"},
+                   "record_bytes": single["r_bytes"], "tuning": list(args.chosen_tuning)},
         "roofline": {"bound": "hbm", "kernel": "k_onesweep (one LSD digit pass)",
                      "achieved": round(rp["achieved"], 1) if rp["achieved"] else None,
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(rp["achieved"] / PEAK_HBM_GBPS, 4) if rp["achieved"] else None,
-                     "traffic": None, "bytes_per_launch": rp["bytes"], "mean_launch_ms": rp["mean_ms"]},
+                     "traffic": measured_traffic(), "bytes_per_launch": rp["bytes"],
+                     "mean_launch_ms": rp["mean_ms"]},
         "cpu_baseline": cpu,
         "kernels": single["kernels"],
         "ms_per_step_profiled": round(single["ms_prof"], 5),

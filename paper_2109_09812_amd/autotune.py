@@ -1,0 +1,150 @@
+"""Autotuner for the radix-sort kernel shape (digit width, workgroup size,
+items per thread).
+
+Every compiled variant computes the identical result, so tuning is purely a
+speed choice. For a given workload shape the tuner runs every variant once,
+checks its outputs bit for bit against variant 0's (a variant that differs is
+a bug and raises), times a few launches with HIP events, and keeps the
+fastest. Results are cached in a JSON file keyed by GPU architecture, record
+width, size bucket and batched/single; a cache with another schema or ABI
+version, or one naming a variant this build does not have, is ignored and
+re-tuned.
+
+Cache path: $MRX_TUNE_CACHE, else ~/.cache/meshrx/tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import statistics
+
+import torch
+
+from . import _lib
+from .api import BatchedReindexer, Reindexer
+
+SCHEMA = 1
+
+
+def cache_path() -> str:
+    return os.environ.get("MRX_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "meshrx", "tune.json")
+
+
+def _arch(device) -> str:
+    try:
+        return str(torch.cuda.get_device_properties(device).gcnArchName).split(":")[0]
+    except Exception:  # pragma: no cover - non-ROCm torch builds
+        return "unknown"
+
+
+def shape_key(arch: str, vtx_bytes: int, num_vtx: int, batched: bool) -> str:
+    bucket = int(math.ceil(math.log2(max(num_vtx, 2))))
+    return f"{arch}|R={vtx_bytes}|n=2^{bucket}|{'batched' if batched else 'single'}"
+
+
+def load_cache(path: str | None = None) -> dict:
+    """Entries of a valid cache file, or {} (missing, corrupt or stale)."""
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if not isinstance(data, dict) or data.get("schema") != SCHEMA:
+        return {}
+    if data.get("abi") != _lib.load().mrx_abi_version():
+        return {}
+    entries = data.get("entries")
+    return entries if isinstance(entries, dict) else {}
+
+
+def save_cache(entries: dict, path: str | None = None):
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump({"schema": SCHEMA, "abi": _lib.load().mrx_abi_version(), "entries": entries}, f, indent=1)
+    os.replace(tmp, path)
+
+
+def cached_tuning(entries: dict, key: str, vtx_bytes: int):
+    """The cached variant for `key` if this build still has it, else None."""
+    e = entries.get(key)
+    if not isinstance(e, dict) or not isinstance(e.get("tuning"), list) or len(e["tuning"]) != 3:
+        return None
+    want = tuple(int(x) for x in e["tuning"])
+    for t in _lib.tunings(vtx_bytes):
+        if t.as_tuple() == want:
+            return t
+    return None
+
+
+def _outputs(r):
+    out = [r.out_vtx, r.out_idx, r.old2new]
+    if getattr(r, "new2old", None) is not None:
+        out.append(r.new2old)
+    if hasattr(r, "out_vtx_offsets"):
+        out.append(r.out_vtx_offsets)
+    else:
+        out.append(r.meta[:1])
+    return out
+
+
+def _time(launch, reps: int) -> float:
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        launch()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return statistics.median(times)
+
+
+def autotune(vtx: torch.Tensor, idx: torch.Tensor, vtx_offsets: torch.Tensor | None = None,
+             elem_offsets: torch.Tensor | None = None, *, reps: int = 5, use_cache: bool = True,
+             path: str | None = None, verbose: bool = False):
+    """Pick the fastest compiled sort variant for this workload shape.
+
+    Returns (tuning, report) where report maps each candidate (d, block,
+    items) to its median milliseconds."""
+    batched = vtx_offsets is not None
+    vtx_bytes = 4 * vtx.shape[1]
+    key = shape_key(_arch(vtx.device), vtx_bytes, vtx.shape[0], batched)
+    entries = load_cache(path) if use_cache else {}
+    hit = cached_tuning(entries, key, vtx_bytes)
+    if hit is not None:
+        return hit, {"cached": entries[key]}
+
+    ref = None
+    report = {}
+    best = None
+    for t in _lib.tunings(vtx_bytes):
+        if batched:
+            r = BatchedReindexer(vtx, vtx_offsets, idx, elem_offsets, tuning=t)
+        else:
+            r = Reindexer(vtx, idx, tuning=t)
+        r.launch()
+        torch.cuda.synchronize()
+        outs = _outputs(r)
+        if ref is None:
+            ref = [o.clone() for o in outs]
+        elif not all(torch.equal(a, b) for a, b in zip(ref, outs)):
+            raise RuntimeError(f"sort variant {t.as_tuple()} disagrees with variant 0")
+        ms = _time(r.launch, reps)
+        report[t.as_tuple()] = ms
+        if verbose:
+            print(f"[autotune] {key} {t.as_tuple()}: {ms:.4f} ms", flush=True)
+        if best is None or ms < best[1]:
+            best = (t, ms)
+        del r
+    if use_cache:
+        entries = load_cache(path)
+        entries[key] = {"tuning": list(best[0].as_tuple()), "ms": best[1],
+                        "candidates": {",".join(map(str, k)): v for k, v in report.items()}}
+        save_cache(entries, path)
+    return best[0], report

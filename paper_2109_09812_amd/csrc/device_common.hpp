@@ -95,33 +95,74 @@ struct Control {
   int64_t num_used;     // U of a batch (all meshes)
 };
 
-// Exclusive prefix over tiles [0, tile) for one bin, by walking back from
-// tile-1 until an inclusive prefix is found. `stride` is the distance in
-// words between consecutive tiles' entries for this bin.
-__device__ __forceinline__ uint32_t lookback_exclusive(const uint64_t* base, int64_t tile,
-                                                       int64_t stride, uint32_t tag,
-                                                       Control* ctl, int32_t* status) {
+// Exclusive prefix over tiles [0, tile) for one bin. The walk reads W
+// predecessor words per step (tile-1 .. tile-W) with independent loads, adds
+// aggregates until it meets an inclusive prefix, and re-polls from the first
+// word that is not published yet. Reading a window per step matters on a
+// multi-die GPU: each agent-scope poll costs a trip to the memory side, so a
+// one-word-per-step walk would let the inclusive prefixes fall behind.
+// `stride` is the distance in words between consecutive tiles' entries.
+template <int W>
+struct LookbackWindow {
+  uint64_t w[W];
+  int64_t hi;  // tile of w[0]; w[i] belongs to tile hi - i
+};
+
+template <int W>
+__device__ __forceinline__ void lookback_issue(LookbackWindow<W>& win, const uint64_t* base, int64_t hi,
+                                               int64_t stride, uint32_t tag) {
+  win.hi = hi;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const int64_t t = hi - i;
+    // below tile 0: a virtual inclusive prefix of 0
+    win.w[i] = t >= 0 ? lb_load(base + t * stride) : lb_pack(kLbInclusive, tag, 0);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t lookback_finish(LookbackWindow<W>& win, const uint64_t* base,
+                                                    int64_t stride, uint32_t tag, Control* ctl,
+                                                    int32_t* status) {
   uint32_t excl = 0;
-  int64_t t = tile - 1;
   uint32_t spins = 0;
-  while (t >= 0) {
-    uint64_t v = lb_load(base + t * stride);
-    uint64_t st = v >> 48;
-    uint32_t vtag = uint32_t(v >> 32) & 0xFFFFu;
-    if (st == 0 || vtag != (tag & 0xFFFFu)) {
+  const uint32_t tag16 = tag & 0xFFFFu;
+  while (true) {
+    int stall = -1;  // first window slot that is not published yet
+    bool done = false;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (done || stall >= 0) continue;
+      const uint64_t v = win.w[i];
+      const uint64_t st = v >> 48;
+      if (st == 0 || (uint32_t(v >> 32) & 0xFFFFu) != tag16) {
+        stall = i;
+        continue;
+      }
+      excl += uint32_t(v);
+      if (st == kLbInclusive) done = true;
+    }
+    if (done) return excl;
+    int64_t next = win.hi - W;
+    if (stall >= 0) {
       if (++spins >= kSpinLimit || flag_load(&ctl->abort)) {
         __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         atomicMax(status, 7 /* MRX_ERR_INTERNAL */);
         return excl;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
+      next = win.hi - stall;
     }
-    excl += uint32_t(v);
-    if (st == kLbInclusive) break;
-    --t;
+    lookback_issue<W>(win, base, next, stride, tag);
   }
-  return excl;
+}
+
+__device__ __forceinline__ uint32_t lookback_exclusive(const uint64_t* base, int64_t tile, int64_t stride,
+                                                       uint32_t tag, Control* ctl, int32_t* status) {
+  if (tile <= 0) return 0;
+  LookbackWindow<1> win;
+  lookback_issue<1>(win, base, tile - 1, stride, tag);
+  return lookback_finish<1>(win, base, stride, tag, ctl, status);
 }
 
 // Dynamic tile id: tiles are claimed in dispatch order, so every tile a

@@ -212,8 +212,8 @@ void set_digit(SortPassArgs& a, int K, int bit) {
   a.shift = bit % 32;
 }
 
-int64_t rand_grid(int64_t work) {
-  return std::max<int64_t>(1, (work + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems));
+int64_t rand_grid(int64_t work, int items = kRandItems) {
+  return std::max<int64_t>(1, (work + kRandBlock * items - 1) / (kRandBlock * items));
 }
 
 mrx_status check_launch() {
@@ -438,7 +438,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     prof_mark("compact", s);
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("old2new", s);
-    hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n)), dim3(kRandBlock), 0, s,
+    hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
                        f.pairs, cmap, n, nullptr, nullptr, 0, old2new);
   }
   // Step 4: remap the index array
@@ -581,7 +581,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
                        static_cast<const Control*>(ctl), static_cast<const int64_t*>(&ctl->num_used), n,
                        out_vtx_offsets);
     prof_mark("old2new", s);
-    hipLaunchKernelGGL((k_scatter_old2new<true>), dim3(rand_grid(n)), dim3(kRandBlock), 0, s,
+    hipLaunchKernelGGL((k_scatter_old2new<true>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
                        f.pairs, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes, old2new);
     if (new2old) {
       prof_mark("localize_new2old", s);

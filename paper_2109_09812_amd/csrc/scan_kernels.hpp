@@ -10,11 +10,13 @@ namespace mrx {
 constexpr int32_t kErrIndex = 3;     // MRX_ERR_INDEX_OUT_OF_RANGE
 constexpr int32_t kErrInternal = 7;  // MRX_ERR_INTERNAL
 
-// Random-access kernels handle kRandItems independent elements per thread:
-// all loads are issued before any dependent access, so each wave keeps
-// several random requests in flight.
-constexpr int kRandItems = 4;
+// Random-access kernels: block size, and independent elements per thread
+// (all loads are issued before any dependent access). The scatter keeps one
+// element per thread: its stores need no loads to wait for, and more waves
+// keep more stores in flight.
 constexpr int kRandBlock = 256;
+constexpr int kRandItems = 4;        // k_mark_used, k_remap
+constexpr int kScatterItems = 1;     // k_scatter_old2new
 
 // Step 1: used[v] = 1 for every referenced vertex v. Batched meshes carry
 // mesh-local indices; the element's mesh supplies the vertex offset.
@@ -282,11 +284,11 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
                                                                 const int64_t* __restrict__ vtx_off,
                                                                 const int64_t* __restrict__ out_off,
                                                                 int32_t nmesh, int32_t* __restrict__ old2new) {
-  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
-  uint2 p[kRandItems];
-  int32_t c[kRandItems];
+  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kScatterItems) + threadIdx.x;
+  uint2 p[kScatterItems];
+  int32_t c[kScatterItems];
 #pragma unroll
-  for (int it = 0; it < kRandItems; ++it) {
+  for (int it = 0; it < kScatterItems; ++it) {
     const int64_t i = base + it * kRandBlock;
     if (i < n) {
       p[it].x = stream_load(&pairs[i].x);
@@ -296,10 +298,10 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
     }
   }
 #pragma unroll
-  for (int it = 0; it < kRandItems; ++it)
+  for (int it = 0; it < kScatterItems; ++it)
     c[it] = (int64_t(p[it].x) < n && int64_t(p[it].y) < n) ? cmap[p[it].x] : -1;
 #pragma unroll
-  for (int it = 0; it < kRandItems; ++it) {
+  for (int it = 0; it < kScatterItems; ++it) {
     if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) continue;  // past the end (or a failed wait)
     int32_t cc = c[it] < 0 ? -1 : c[it];
     if constexpr (BATCHED) {

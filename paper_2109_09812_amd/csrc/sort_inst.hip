@@ -85,6 +85,8 @@ void MRX_CAT(register_k, MRX_INST_K)(std::vector<SortVariant>& out) {
   out.push_back(make<8, 256, 12>());
   out.push_back(make<8, 512, 8>());
   out.push_back(make<8, 1024, 8>());
+  out.push_back(make<9, 256, 16>());
+  out.push_back(make<9, 512, 8>());
 #elif MRX_INST_K == 8
   out.push_back(make<8, 512, 8>());
   out.push_back(make<8, 256, 6>());

@@ -283,8 +283,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   }
   __syncthreads();
 
-  // ---- per-digit tile totals; wave counters become wave-exclusive offsets
-  uint32_t tot[BPT];
+  // ---- per-digit tile totals; wave counters become wave-exclusive offsets.
+  // The tile's counts are published at once, and the first look-back window
+  // (the predecessor tiles' words) is requested now but examined only after
+  // the LDS reorder below, so its latency overlaps that work.
+  constexpr int LBW = 8;  // look-back window: predecessor tiles read per poll
+  uint32_t tot[BPT], start_of[BPT];
+  LookbackWindow<LBW> probe[BPT];
   uint32_t my_sum = 0;
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
@@ -297,9 +302,9 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
         s_hist[w * RADIX + bin] = run;
         run += c;
       }
-      // publish this tile's count as early as possible
       lb_store(a.lookback + int64_t(tile) * RADIX + bin,
                lb_pack(tile == 0 ? kLbInclusive : kLbAggregate, a.tag, run));
+      if (tile != 0) lookback_issue<LBW>(probe[k], a.lookback + bin, int64_t(tile) - 1, RADIX, a.tag);
     }
     tot[k] = run;
     my_sum += run;
@@ -309,15 +314,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const int bin = tid * BPT + k;
-    if (bin < RADIX) {
-      uint32_t prev = 0;
-      if (tile != 0) {
-        prev = lookback_exclusive(a.lookback + bin, tile, RADIX, a.tag, a.ctl, a.status);
-        lb_store(a.lookback + int64_t(tile) * RADIX + bin, lb_pack(kLbInclusive, a.tag, prev + tot[k]));
-      }
-      s_start[bin] = start;
-      s_base[bin] = a.bucket_base[bin] + prev - start;  // wraps; base + local position is exact
-    }
+    if (bin < RADIX) s_start[bin] = start;
+    start_of[k] = start;
     start += tot[k];
   }
   __syncthreads();
@@ -329,13 +327,6 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       rank[j] += s_start[dig[j]] + my_hist[dig[j]];
       s_dig[rank[j]] = uint16_t(dig[j]);
     }
-  }
-  __syncthreads();
-  uint32_t opos[IPT];
-#pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    const int q = r * BLOCK + tid;
-    opos[r] = q < valid_count ? s_base[s_dig[q]] + uint32_t(q) : 0xFFFFFFFFu;
   }
 
   // ---- reorder one word plane at a time through LDS (double-buffered)
@@ -352,6 +343,27 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       const int q = r * BLOCK + tid;
       if (q < valid_count) v[r][w] = buf[q];
     }
+  }
+
+  // ---- finish the look-back: global start of each digit's run in this tile
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int bin = tid * BPT + k;
+    if (bin < RADIX) {
+      uint32_t prev = 0;
+      if (tile != 0) {
+        prev = lookback_finish<LBW>(probe[k], a.lookback + bin, RADIX, a.tag, a.ctl, a.status);
+        lb_store(a.lookback + int64_t(tile) * RADIX + bin, lb_pack(kLbInclusive, a.tag, prev + tot[k]));
+      }
+      s_base[bin] = a.bucket_base[bin] + prev - start_of[k];  // wraps; base + local position is exact
+    }
+  }
+  __syncthreads();
+  uint32_t opos[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int q = r * BLOCK + tid;
+    opos[r] = q < valid_count ? s_base[s_dig[q]] + uint32_t(q) : 0xFFFFFFFFu;
   }
 
   // ---- scatter: consecutive q of one digit go to consecutive addresses

@@ -116,7 +116,7 @@ def _call(**kw):
     (dict(old2new=C + 8), _lib.MRX_ERR_INVALID_ARGUMENT),      # overlaps out_vtx
     (dict(out_idx=E), _lib.MRX_ERR_INVALID_ARGUMENT),          # out_idx == old2new
     (dict(new2old=W + 4096), _lib.MRX_ERR_INVALID_ARGUMENT),   # inside the workspace
-    (dict(tuning=(9, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
+    (dict(tuning=(10, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
 ])
 def test_reindex_rejects_bad_arguments(kw, expected):
     assert _call(**kw) == expected
@@ -156,3 +156,30 @@ def test_gather_rejects_bad_arguments():
     assert gb(A, 5, 16, 0, B, 10, None, 1, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT
     assert gb(A, 5, 16, 0, B, 10, C + 4, 1, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT
     assert gb(A, 5, 16, 1, B, 10, A, 1, None, None) == _lib.MRX_ERR_INVALID_ARGUMENT   # overlap
+
+
+# ----------------------------------------------------------------- autotune cache (host logic)
+
+def test_autotune_cache_validation(tmp_path, monkeypatch):
+    import json
+    from paper_2109_09812_amd import autotune as at
+    path = str(tmp_path / "tune.json")
+    assert at.load_cache(path) == {}                       # missing
+    open(path, "w").write("{not json")
+    assert at.load_cache(path) == {}                       # corrupt
+    json.dump({"schema": 99, "abi": 1, "entries": {"k": {}}}, open(path, "w"))
+    assert at.load_cache(path) == {}                       # other schema
+    json.dump({"schema": at.SCHEMA, "abi": 999, "entries": {"k": {}}}, open(path, "w"))
+    assert at.load_cache(path) == {}                       # other ABI
+    t0 = _lib.tunings(12)[0].as_tuple()
+    entries = {"a": {"tuning": list(t0)}, "b": {"tuning": [7, 333, 5]}, "c": {"tuning": "x"}}
+    at.save_cache(entries, path)
+    loaded = at.load_cache(path)
+    assert loaded == json.loads(json.dumps(entries))
+    assert at.cached_tuning(loaded, "a", 12).as_tuple() == t0
+    assert at.cached_tuning(loaded, "b", 12) is None       # variant not in this build
+    assert at.cached_tuning(loaded, "c", 12) is None       # malformed
+    assert at.cached_tuning(loaded, "missing", 12) is None
+    k = at.shape_key("gfx950", 12, 26_398_316, False)
+    assert k == "gfx950|R=12|n=2^25|single"
+    assert at.shape_key("gfx950", 12, 1000, True).endswith("|batched")

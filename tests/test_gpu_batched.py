@@ -128,3 +128,16 @@ def test_graph_replays_with_new_contents():
         check_batch(b, gr.result())
         # eager work between replays
         _ = (tensors[0].float() * 2).sum().item()
+
+
+def test_batched_all_tunings_and_autotune(tmp_path):
+    import paper_2109_09812_amd as mrx
+    from paper_2109_09812_amd import autotune
+    b = meshgen.batched(50, 100, 6000, 0.05, 515)
+    tensors = to_dev(b)
+    for t in mrx.tunings(12):
+        _say("batched tuning", t.as_tuple())
+        check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=t))
+    t, report = autotune.autotune(tensors[0], tensors[2], tensors[1], tensors[3], reps=2,
+                                  path=str(tmp_path / "t.json"))
+    check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=t))

@@ -207,3 +207,21 @@ def test_cfg2_soup2048_properties():
     sov, _, _, sn2o = oracle.reindex(sub_vtx, sub_idx)
     assert np.array_equal(sov, sel_vals)
     assert np.array_equal(members[sn2o], got[3][np.sort(pick)])
+
+
+def test_autotune_picks_a_verified_variant(tmp_path):
+    """The tuner runs every compiled variant, checks each against variant 0
+    bit for bit, and its choice reproduces the oracle's result."""
+    import paper_2109_09812_amd as mrx
+    from paper_2109_09812_amd import autotune
+    m = meshgen.grid_soup(400, 0.05, 4242, "tune")
+    v, i = to_dev(m.vtx, m.idx)
+    _say("autotune")
+    t, report = autotune.autotune(v, i, reps=2, path=str(tmp_path / "t.json"))
+    assert t.as_tuple() in report and len(report) == len(mrx.tunings(12))
+    t2, rep2 = autotune.autotune(v, i, reps=2, path=str(tmp_path / "t.json"))
+    assert t2.as_tuple() == t.as_tuple() and "cached" in rep2
+    got = gpu(m.vtx, m.idx, tuning=t)
+    exp = oracle.reindex(m.vtx, m.idx)
+    for g, e in zip(got, exp):
+        assert np.array_equal(g, e)
