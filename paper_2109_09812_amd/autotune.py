@@ -82,13 +82,13 @@ def cached_tuning(entries: dict, key: str, vtx_bytes: int):
 
 
 def _outputs(r):
-    out = [r.out_vtx, r.out_idx, r.old2new]
-    if getattr(r, "new2old", None) is not None:
-        out.append(r.new2old)
-    if hasattr(r, "out_vtx_offsets"):
-        out.append(r.out_vtx_offsets)
-    else:
-        out.append(r.meta[:1])
+    """The defined part of a launch's outputs (capacity beyond U is not)."""
+    res = r.result()
+    out = [res.out_vtx, res.out_idx, res.old2new]
+    if res.new2old is not None:
+        out.append(res.new2old)
+    if hasattr(res, "out_vtx_offsets"):
+        out.append(res.out_vtx_offsets)
     return out
 
 

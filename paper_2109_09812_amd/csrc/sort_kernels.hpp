@@ -287,14 +287,22 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // The tile's counts are published at once, and the first look-back window
   // (the predecessor tiles' words) is requested now but examined only after
   // the LDS reorder below, so its latency overlaps that work.
-  constexpr int LBW = 8;  // look-back window: predecessor tiles read per poll
+#ifndef MRX_LBW
+#define MRX_LBW 4
+#endif
+  constexpr int LBW = MRX_LBW;  // look-back window: predecessor tiles read per poll
+  // Digits that no element of the whole pass carries (the global histogram
+  // says so) are skipped by every tile alike: nothing is published for them
+  // and nobody waits on them.
   uint32_t tot[BPT], start_of[BPT];
+  bool live[BPT];
   LookbackWindow<LBW> probe[BPT];
   uint32_t my_sum = 0;
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const int bin = tid * BPT + k;
     uint32_t run = 0;
+    live[k] = false;
     if (bin < RADIX) {
 #pragma unroll
       for (int w = 0; w < WAVES; ++w) {
@@ -302,9 +310,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
         s_hist[w * RADIX + bin] = run;
         run += c;
       }
-      lb_store(a.lookback + int64_t(tile) * RADIX + bin,
-               lb_pack(tile == 0 ? kLbInclusive : kLbAggregate, a.tag, run));
-      if (tile != 0) lookback_issue<LBW>(probe[k], a.lookback + bin, int64_t(tile) - 1, RADIX, a.tag);
+      const uint32_t gend = bin + 1 < RADIX ? a.bucket_base[bin + 1] : uint32_t(n);
+      live[k] = gend != a.bucket_base[bin];
+      if (live[k]) {
+        lb_store(a.lookback + int64_t(tile) * RADIX + bin,
+                 lb_pack(tile == 0 ? kLbInclusive : kLbAggregate, a.tag, run));
+        if (tile != 0) lookback_issue<LBW>(probe[k], a.lookback + bin, int64_t(tile) - 1, RADIX, a.tag);
+      }
     }
     tot[k] = run;
     my_sum += run;
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
     const int bin = tid * BPT + k;
     if (bin < RADIX) {
       uint32_t prev = 0;
-      if (tile != 0) {
+      if (tile != 0 && live[k]) {
         prev = lookback_finish<LBW>(probe[k], a.lookback + bin, RADIX, a.tag, a.ctl, a.status);
         lb_store(a.lookback + int64_t(tile) * RADIX + bin, lb_pack(kLbInclusive, a.tag, prev + tot[k]));
       }
