@@ -57,16 +57,21 @@ typedef enum {
   MRX_ERR_INTERNAL = 7             /* (device) a cross-workgroup wait hit its bound; results invalid */
 } mrx_status;
 
-/* Kernel-shape knobs of the radix sort. All-zero fields mean "built-in
+/* Kernel-shape knobs of the radix sort. All-zero shape fields mean "built-in
  * default for this record width". Only compiled combinations are accepted;
- * mrx_tuning_count/mrx_tuning_get enumerate them. Every variant returns the
- * identical result. */
+ * mrx_tuning_count/mrx_tuning_get enumerate them. Every variant, with any
+ * flags, returns the identical result. */
 typedef struct {
   int32_t digit_bits;       /* radix digit width d of the LSD passes */
   int32_t block_threads;    /* workgroup size of the sort passes (multiple of 64) */
   int32_t items_per_thread; /* keys per thread per sort tile */
-  int32_t reserved;         /* must be 0 */
+  int32_t flags;            /* MRX_TUNING_* bits; unknown bits are rejected */
 } mrx_tuning;
+
+/* The decoupled look-back of the sort passes keeps one word per (tile,
+ * digit). By default those words are 32 bits (counts below 2^30); with this
+ * flag, or whenever num_vtx >= 2^30, 64-bit words are used instead. */
+#define MRX_TUNING_WIDE_LOOKBACK 1
 
 /* Library ABI version (MRX_ABI_VERSION of the build). */
 int32_t mrx_abi_version(void);

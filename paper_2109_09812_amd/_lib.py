@@ -29,11 +29,15 @@ EXPORTS = (
 )
 
 
+MRX_TUNING_WIDE_LOOKBACK = 1
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("items_per_thread", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("items_per_thread", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
     def as_tuple(self):
+        """The kernel shape (flags excluded)."""
         return (self.digit_bits, self.block_threads, self.items_per_thread)
 
 
@@ -112,8 +116,8 @@ def make_tuning(t) -> ctypes.POINTER(Tuning) | None:
         return None
     if isinstance(t, Tuning):
         return ctypes.pointer(t)
-    d, b, i = t
-    return ctypes.pointer(Tuning(d, b, i, 0))
+    d, b, i, *rest = t
+    return ctypes.pointer(Tuning(d, b, i, rest[0] if rest else 0))
 
 
 def profile_enable(on: bool = True):

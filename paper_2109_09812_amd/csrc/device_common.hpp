@@ -55,26 +55,52 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 
 // ---------------------------------------------------------------- look-back
 //
-// Decoupled look-back state: one 64-bit word per (tile, bin).
-//   bits  0..31  value (a count, < 2^31)
-//   bits 32..47  tag   (which launch of the call wrote it; 0 = cleared)
-//   bits 48..49  status: 1 = tile aggregate only, 2 = inclusive prefix
-// The value travels inside the same atomic word as its status, so relaxed
-// agent-scope atomics suffice: no other memory is published through it.
+// Decoupled look-back state: one word per (tile, bin) holding a status
+// (0 = not published, 1 = tile aggregate only, 2 = inclusive prefix) and a
+// count. The value travels inside the same atomic word as its status, so
+// relaxed agent-scope atomics suffice: no other memory is published through
+// it. Two word formats:
+//   LbTagged  (64 bit): value bits 0..31, tag bits 32..47 (which launch of the
+//             call wrote it), status bits 48..49. A word written by an earlier
+//             launch of the same call carries another tag and reads as "not
+//             published", so launches can share one zeroed buffer.
+//   LbCompact (32 bit): value bits 0..29, status bits 30..31. No tag: each
+//             launch needs a buffer cleared since the last launch that used
+//             it. Half the polling traffic; values must stay below 2^30.
 
-constexpr uint64_t kLbAggregate = 1;
-constexpr uint64_t kLbInclusive = 2;
+constexpr uint32_t kLbAggregate = 1;
+constexpr uint32_t kLbInclusive = 2;
 
-__device__ __forceinline__ uint64_t lb_pack(uint64_t status, uint32_t tag, uint32_t value) {
-  return (status << 48) | (uint64_t(tag & 0xFFFFu) << 32) | uint64_t(value);
-}
+struct LbTagged {
+  using Word = uint64_t;
+  static __device__ __forceinline__ Word pack(uint32_t st, uint32_t tag, uint32_t value) {
+    return (uint64_t(st) << 48) | (uint64_t(tag & 0xFFFFu) << 32) | uint64_t(value);
+  }
+  // status of a word for a reader of launch `tag` (0 if written by another launch)
+  static __device__ __forceinline__ uint32_t status(Word w, uint32_t tag) {
+    return (uint32_t(w >> 32) & 0xFFFFu) == (tag & 0xFFFFu) ? uint32_t(w >> 48) : 0u;
+  }
+  static __device__ __forceinline__ uint32_t value(Word w) { return uint32_t(w); }
+};
 
-__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+struct LbCompact {
+  using Word = uint32_t;
+  static constexpr uint32_t kMaxValue = (1u << 30) - 1;
+  static __device__ __forceinline__ Word pack(uint32_t st, uint32_t, uint32_t value) {
+    return (st << 30) | value;
+  }
+  static __device__ __forceinline__ uint32_t status(Word w, uint32_t) { return w >> 30; }
+  static __device__ __forceinline__ uint32_t value(Word w) { return w & kMaxValue; }
+};
+
+template <typename W>
+__device__ __forceinline__ void lb_store(W* p, W v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <typename W>
+__device__ __forceinline__ W lb_load(const W* p) {
+  return __hip_atomic_load(const_cast<W*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int32_t flag_load(const int32_t* p) {
@@ -102,44 +128,42 @@ struct Control {
 // multi-die GPU: each agent-scope poll costs a trip to the memory side, so a
 // one-word-per-step walk would let the inclusive prefixes fall behind.
 // `stride` is the distance in words between consecutive tiles' entries.
-template <int W>
+template <int W, typename C>
 struct LookbackWindow {
-  uint64_t w[W];
+  typename C::Word w[W];
   int64_t hi;  // tile of w[0]; w[i] belongs to tile hi - i
 };
 
-template <int W>
-__device__ __forceinline__ void lookback_issue(LookbackWindow<W>& win, const uint64_t* base, int64_t hi,
-                                               int64_t stride, uint32_t tag) {
+template <int W, typename C>
+__device__ __forceinline__ void lookback_issue(LookbackWindow<W, C>& win, const typename C::Word* base,
+                                               int64_t hi, int64_t stride, uint32_t tag) {
   win.hi = hi;
 #pragma unroll
   for (int i = 0; i < W; ++i) {
     const int64_t t = hi - i;
     // below tile 0: a virtual inclusive prefix of 0
-    win.w[i] = t >= 0 ? lb_load(base + t * stride) : lb_pack(kLbInclusive, tag, 0);
+    win.w[i] = t >= 0 ? lb_load(base + t * stride) : C::pack(kLbInclusive, tag, 0);
   }
 }
 
-template <int W>
-__device__ __forceinline__ uint32_t lookback_finish(LookbackWindow<W>& win, const uint64_t* base,
+template <int W, typename C>
+__device__ __forceinline__ uint32_t lookback_finish(LookbackWindow<W, C>& win, const typename C::Word* base,
                                                     int64_t stride, uint32_t tag, Control* ctl,
                                                     int32_t* status) {
   uint32_t excl = 0;
   uint32_t spins = 0;
-  const uint32_t tag16 = tag & 0xFFFFu;
   while (true) {
     int stall = -1;  // first window slot that is not published yet
     bool done = false;
 #pragma unroll
     for (int i = 0; i < W; ++i) {
       if (done || stall >= 0) continue;
-      const uint64_t v = win.w[i];
-      const uint64_t st = v >> 48;
-      if (st == 0 || (uint32_t(v >> 32) & 0xFFFFu) != tag16) {
+      const uint32_t st = C::status(win.w[i], tag);
+      if (st == 0) {
         stall = i;
         continue;
       }
-      excl += uint32_t(v);
+      excl += C::value(win.w[i]);
       if (st == kLbInclusive) done = true;
     }
     if (done) return excl;
@@ -153,16 +177,16 @@ __device__ __forceinline__ uint32_t lookback_finish(LookbackWindow<W>& win, cons
       __builtin_amdgcn_s_sleep(1);
       next = win.hi - stall;
     }
-    lookback_issue<W>(win, base, next, stride, tag);
+    lookback_issue<W, C>(win, base, next, stride, tag);
   }
 }
 
 __device__ __forceinline__ uint32_t lookback_exclusive(const uint64_t* base, int64_t tile, int64_t stride,
                                                        uint32_t tag, Control* ctl, int32_t* status) {
   if (tile <= 0) return 0;
-  LookbackWindow<1> win;
-  lookback_issue<1>(win, base, tile - 1, stride, tag);
-  return lookback_finish<1>(win, base, stride, tag, ctl, status);
+  LookbackWindow<1, LbTagged> win;
+  lookback_issue<1, LbTagged>(win, base, tile - 1, stride, tag);
+  return lookback_finish<1, LbTagged>(win, base, stride, tag, ctl, status);
 }
 
 // Dynamic tile id: tiles are claimed in dispatch order, so every tile a

@@ -119,12 +119,20 @@ const std::vector<SortVariant>& variants_for(int K) {
   return (K >= 1 && K <= 16) ? table[K] : empty;
 }
 
-// Picks the variant a tuning asks for; all-zero (or NULL) = variant 0.
+// Sort passes use 32-bit look-back words unless a count could reach 2^30
+// (or the caller asks for the 64-bit words).
+constexpr int64_t kCompactLookbackLimit = int64_t(1) << 30;
+bool wide_lookback(int64_t n, const mrx_tuning* t) {
+  return n >= kCompactLookbackLimit || (t && (t->flags & MRX_TUNING_WIDE_LOOKBACK));
+}
+
+// Picks the variant a tuning asks for; all-zero shape (or NULL) = variant 0.
+// Unknown flag bits are rejected.
 const SortVariant* pick_variant(int K, const mrx_tuning* t) {
   const auto& vs = variants_for(K);
   if (vs.empty()) return nullptr;
+  if (t && (t->flags & ~int32_t(MRX_TUNING_WIDE_LOOKBACK)) != 0) return nullptr;
   if (!t || (t->digit_bits == 0 && t->block_threads == 0 && t->items_per_thread == 0)) return &vs[0];
-  if (t->reserved != 0) return nullptr;
   for (const auto& v : vs)
     if (v.D == t->digit_bits && v.block == t->block_threads && v.ipt == t->items_per_thread) return &v;
   return nullptr;
@@ -140,7 +148,7 @@ struct Layout {
   int K = 0, S = 0, P_key = 0, P_mesh = 0;
   int64_t tiles_sort = 0, tiles_scan = 0;
   // zeroed region
-  size_t ctl = 0, counters = 0, hist = 0, lookback = 0, used_v = 0, used_g = 0, zero_end = 0;
+  size_t ctl = 0, counters = 0, hist = 0, lookback = 0, scan_lookback = 0, used_v = 0, used_g = 0, zero_end = 0;
   // scratch
   size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, total = 0;
 };
@@ -158,8 +166,11 @@ Layout make_layout(int64_t n, int K, int32_t nmesh, const SortVariant& v) {
   L.ctl = off;      off = align_up(off + sizeof(Control));
   L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + 2));
   L.hist = off;     off = align_up(off + sizeof(uint32_t) * size_t(P) * size_t(v.radix()));
-  const int64_t lb_words = std::max<int64_t>({L.tiles_sort * v.radix(), L.tiles_scan, 1});
+  // sort look-back: tiles x radix 64-bit words, or two alternating buffers of
+  // 32-bit words in the same bytes; flag scan and compaction have their own
+  const int64_t lb_words = std::max<int64_t>(L.tiles_sort * v.radix(), 1);
   L.lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(lb_words));
+  L.scan_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_scan + 1));
   L.used_v = off;   off = align_up(off + size_t(n));
   L.used_g = off;   off = align_up(off + size_t(n));
   L.zero_end = off;
@@ -273,7 +284,7 @@ mrx_status mrx_tuning_get(int32_t vtx_bytes, int32_t i, mrx_tuning* out) {
   out->digit_bits = v.D;
   out->block_threads = v.block;
   out->items_per_thread = v.ipt;
-  out->reserved = 0;
+  out->flags = 0;
   return MRX_OK;
 }
 
@@ -360,6 +371,10 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
   uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
+  const bool wide = wide_lookback(n, tuning);
+  uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
+                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
   uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
   uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
@@ -392,7 +407,8 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
       a.dst = buf[cur];
       a.used = used_v;
       a.bucket_base = hist + size_t(p) * v.radix();
-      a.lookback = lookback;
+      a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
+      a.lookback_next = lb32[(p + 1) & 1];
       a.tile_counter = counters + p;
       a.ctl = ctl;
       a.status = status;
@@ -400,7 +416,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
       set_digit(a, K, p * v.D);
       a.tag = uint32_t(p + 1);
       prof_mark(p == 0 ? "onesweep_first" : "onesweep", s);
-      v.pass(a, p == 0 ? kPassFirst : kPassKey, L.tiles_sort, s);
+      v.pass(a, p == 0 ? kPassFirst : kPassKey, wide, L.tiles_sort, s);
       src = buf[cur];
       cur ^= 1;
     }
@@ -412,7 +428,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     f.uniq = uniq;
     f.rep = rep;
     f.used_g = used_g;
-    f.lookback = lookback;
+    f.lookback = scan_lookback;
     f.tile_counter = counters + L.P_key;
     f.ctl = ctl;
     f.status = status;
@@ -430,7 +446,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     c.cmap = cmap;
     c.out_num = out_num_vtx;
     c.cap = n;
-    c.lookback = lookback;
+    c.lookback = scan_lookback;
     c.tile_counter = counters + L.P_key + 1;
     c.ctl = ctl;
     c.status = status;
@@ -488,6 +504,10 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
+  const bool wide = wide_lookback(n, tuning);
+  uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
+                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
   uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
   uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
@@ -521,7 +541,8 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
       a.dst = buf[cur];
       a.used = used_v;
       a.bucket_base = hist + size_t(p) * v.radix();
-      a.lookback = lookback;
+      a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
+      a.lookback_next = lb32[(p + 1) & 1];
       a.tile_counter = counters + p;
       a.ctl = ctl;
       a.status = status;
@@ -538,7 +559,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
         mode = kPassMesh;
       }
       prof_mark(mode == kPassFirst ? "onesweep_first" : mode == kPassMesh ? "onesweep_mesh" : "onesweep", s);
-      v.pass(a, mode, L.tiles_sort, s);
+      v.pass(a, mode, wide, L.tiles_sort, s);
       src = buf[cur];
       cur ^= 1;
     }
@@ -549,7 +570,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     f.uniq = uniq;
     f.rep = rep;
     f.used_g = used_g;
-    f.lookback = lookback;
+    f.lookback = scan_lookback;
     f.tile_counter = counters + P;
     f.ctl = ctl;
     f.status = status;
@@ -568,7 +589,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     c.cmap = cmap;
     c.out_num = &ctl->num_used;
     c.cap = n;
-    c.lookback = lookback;
+    c.lookback = scan_lookback;
     c.tile_counter = counters + P + 1;
     c.ctl = ctl;
     c.status = status;

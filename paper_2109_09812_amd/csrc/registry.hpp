@@ -18,8 +18,9 @@ constexpr int kScanTile = kScanBlock * kScanIpt;
 
 struct SortVariant {
   int K = 0, D = 0, block = 0, ipt = 0;
-  // one LSD pass over `grid` tiles
-  void (*pass)(const SortPassArgs&, int mode, int64_t grid, hipStream_t) = nullptr;
+  // one LSD pass over `grid` tiles; `wide` selects 64-bit tagged look-back
+  // words (needed once counts can reach 2^30), else 32-bit ones
+  void (*pass)(const SortPassArgs&, int mode, bool wide, int64_t grid, hipStream_t) = nullptr;
   // digit histograms of all key passes
   void (*hist)(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t) = nullptr;
   // digit histograms of the mesh-id passes of a batch

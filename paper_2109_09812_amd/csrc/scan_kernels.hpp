@@ -151,12 +151,12 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
   if (tid == 0) {
     uint64_t* lb = a.lookback + tile;
     if (tile == 0) {
-      lb_store(lb, lb_pack(kLbInclusive, a.tag, tile_total));
+      lb_store(lb, LbTagged::pack(kLbInclusive, a.tag, tile_total));
       s_prefix = 0;
     } else {
-      lb_store(lb, lb_pack(kLbAggregate, a.tag, tile_total));
+      lb_store(lb, LbTagged::pack(kLbAggregate, a.tag, tile_total));
       const uint32_t prev = lookback_exclusive(a.lookback, tile, 1, a.tag, a.ctl, a.status);
-      lb_store(lb, lb_pack(kLbInclusive, a.tag, prev + tile_total));
+      lb_store(lb, LbTagged::pack(kLbInclusive, a.tag, prev + tile_total));
       s_prefix = prev;
     }
   }
@@ -245,12 +245,12 @@ __global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
   if (tid == 0) {
     uint64_t* lb = a.lookback + tile;
     if (tile == 0) {
-      lb_store(lb, lb_pack(kLbInclusive, a.tag, tile_total));
+      lb_store(lb, LbTagged::pack(kLbInclusive, a.tag, tile_total));
       s_prefix = 0;
     } else {
-      lb_store(lb, lb_pack(kLbAggregate, a.tag, tile_total));
+      lb_store(lb, LbTagged::pack(kLbAggregate, a.tag, tile_total));
       const uint32_t prev = lookback_exclusive(a.lookback, tile, 1, a.tag, a.ctl, a.status);
-      lb_store(lb, lb_pack(kLbInclusive, a.tag, prev + tile_total));
+      lb_store(lb, LbTagged::pack(kLbInclusive, a.tag, prev + tile_total));
       s_prefix = prev;
     }
   }

@@ -16,20 +16,28 @@ namespace {
 
 constexpr int K = MRX_INST_K;
 
-template <int D, int BLOCK, int IPT>
-void launch_pass(const SortPassArgs& a, int mode, int64_t grid, hipStream_t s) {
-  if (grid <= 0) return;
+template <int D, int BLOCK, int IPT, bool WIDE>
+void launch_pass_w(const SortPassArgs& a, int mode, int64_t grid, hipStream_t s) {
   switch (mode) {
     case kPassFirst:
-      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassFirst>), dim3(grid), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassFirst, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
     case kPassKey:
-      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassKey>), dim3(grid), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassKey, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassMesh>), dim3(grid), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassMesh, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
   }
+}
+
+template <int D, int BLOCK, int IPT>
+void launch_pass(const SortPassArgs& a, int mode, bool wide, int64_t grid, hipStream_t s) {
+  if (grid <= 0) return;
+  if (wide)
+    launch_pass_w<D, BLOCK, IPT, true>(a, mode, grid, s);
+  else
+    launch_pass_w<D, BLOCK, IPT, false>(a, mode, grid, s);
 }
 
 template <int D>

@@ -8,6 +8,8 @@
 // run of equal records is the copy with the smallest original id.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace mrx {
@@ -19,7 +21,11 @@ struct SortPassArgs {
   uint32_t* dst;                // elements (K+1 words)
   const uint8_t* used;          // first pass: 1 if some index entry references the vertex
   const uint32_t* bucket_base;  // [RADIX] start of each digit's bucket in dst
-  uint64_t* lookback;           // [tiles][RADIX]
+  // Look-back words, [tiles][RADIX]: LbTagged words (wide launches), or
+  // LbCompact words in `lookback` with `lookback_next` the buffer of the
+  // next launch, which this launch clears.
+  void* lookback;
+  uint32_t* lookback_next;
   uint32_t* tile_counter;
   Control* ctl;
   int32_t* status;
@@ -198,8 +204,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_buckets(uint32_t* __restrict__ h
 // digit's global offset. Elements are reordered through LDS into digit
 // order, one 32-bit word plane at a time, so each thread writes runs of
 // consecutive addresses.
-template <int K, int D, int BLOCK, int IPT, int MODE>
+template <int K, int D, int BLOCK, int IPT, int MODE, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
+  using LB = typename std::conditional<WIDE, LbTagged, LbCompact>::type;
+  using LbWord = typename LB::Word;
+  LbWord* const lookback = static_cast<LbWord*>(a.lookback);
   constexpr int S = K + 1;
   constexpr int RADIX = 1 << D;
   constexpr uint32_t MASK = RADIX - 1;
@@ -287,16 +296,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // The tile's counts are published at once, and the first look-back window
   // (the predecessor tiles' words) is requested now but examined only after
   // the LDS reorder below, so its latency overlaps that work.
-#ifndef MRX_LBW
-#define MRX_LBW 4
-#endif
-  constexpr int LBW = MRX_LBW;  // look-back window: predecessor tiles read per poll
+  constexpr int LBW = 4;  // look-back window: predecessor tiles read per poll
   // Digits that no element of the whole pass carries (the global histogram
   // says so) are skipped by every tile alike: nothing is published for them
   // and nobody waits on them.
   uint32_t tot[BPT], start_of[BPT];
   bool live[BPT];
-  LookbackWindow<LBW> probe[BPT];
+  LookbackWindow<LBW, LB> probe[BPT];
   uint32_t my_sum = 0;
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
@@ -310,12 +316,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
         s_hist[w * RADIX + bin] = run;
         run += c;
       }
+      if constexpr (!WIDE) lb_store(a.lookback_next + int64_t(tile) * RADIX + bin, 0u);
       const uint32_t gend = bin + 1 < RADIX ? a.bucket_base[bin + 1] : uint32_t(n);
       live[k] = gend != a.bucket_base[bin];
       if (live[k]) {
-        lb_store(a.lookback + int64_t(tile) * RADIX + bin,
-                 lb_pack(tile == 0 ? kLbInclusive : kLbAggregate, a.tag, run));
-        if (tile != 0) lookback_issue<LBW>(probe[k], a.lookback + bin, int64_t(tile) - 1, RADIX, a.tag);
+        lb_store(lookback + int64_t(tile) * RADIX + bin,
+                 LB::pack(tile == 0 ? kLbInclusive : kLbAggregate, a.tag, run));
+        if (tile != 0) lookback_issue<LBW, LB>(probe[k], lookback + bin, int64_t(tile) - 1, RADIX, a.tag);
       }
     }
     tot[k] = run;
@@ -364,8 +371,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
     if (bin < RADIX) {
       uint32_t prev = 0;
       if (tile != 0 && live[k]) {
-        prev = lookback_finish<LBW>(probe[k], a.lookback + bin, RADIX, a.tag, a.ctl, a.status);
-        lb_store(a.lookback + int64_t(tile) * RADIX + bin, lb_pack(kLbInclusive, a.tag, prev + tot[k]));
+        prev = lookback_finish<LBW, LB>(probe[k], lookback + bin, RADIX, a.tag, a.ctl, a.status);
+        lb_store(lookback + int64_t(tile) * RADIX + bin, LB::pack(kLbInclusive, a.tag, prev + tot[k]));
       }
       s_base[bin] = a.bucket_base[bin] + prev - start_of[k];  // wraps; base + local position is exact
     }
