@@ -11,12 +11,12 @@ constexpr int32_t kErrIndex = 3;     // MRX_ERR_INDEX_OUT_OF_RANGE
 constexpr int32_t kErrInternal = 7;  // MRX_ERR_INTERNAL
 
 // Random-access kernels: block size, and independent elements per thread
-// (all loads are issued before any dependent access). The scatter keeps one
-// element per thread: its stores need no loads to wait for, and more waves
-// keep more stores in flight.
+// (all loads are issued before any dependent access). Measured on a 26.4M-
+// vertex soup: the old2new scatter needs many (pair load, id lookup, store)
+// chains in flight per thread; the index kernels gain nothing beyond two.
 constexpr int kRandBlock = 256;
-constexpr int kRandItems = 4;        // k_mark_used, k_remap
-constexpr int kScatterItems = 1;     // k_scatter_old2new
+constexpr int kRandItems = 2;        // k_mark_used, k_remap
+constexpr int kScatterItems = 16;    // k_scatter_old2new
 
 // Step 1: used[v] = 1 for every referenced vertex v. Batched meshes carry
 // mesh-local indices; the element's mesh supplies the vertex offset.
@@ -291,8 +291,7 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
   for (int it = 0; it < kScatterItems; ++it) {
     const int64_t i = base + it * kRandBlock;
     if (i < n) {
-      p[it].x = stream_load(&pairs[i].x);
-      p[it].y = stream_load(&pairs[i].y);
+      p[it] = pairs[i];  // one 8-byte load
     } else {
       p[it] = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
     }
