@@ -73,6 +73,14 @@ typedef struct {
  * flag, or whenever num_vtx >= 2^30, 64-bit words are used instead. */
 #define MRX_TUNING_WIDE_LOOKBACK 1
 
+/* Kernels whose tiles wait on preceding tiles (decoupled look-back) by default
+ * number their tiles by workgroup id, relying on every die of the GPU
+ * dispatching its workgroups in increasing id order (a broken assumption
+ * would surface as MRX_ERR_INTERNAL, never as a hang). With this flag the
+ * tiles are instead claimed from a counter in arrival order, which needs no
+ * assumption about dispatch order but costs a round trip per tile. */
+#define MRX_TUNING_CLAIMED_TILES 2
+
 /* Library ABI version (MRX_ABI_VERSION of the build). */
 int32_t mrx_abi_version(void);
 

@@ -5,9 +5,9 @@ run-head flags, prefix sums, scatters, index remap).
 The compute lives in libmeshrx.so (hand-written HIP for gfx950, C ABI in
 include/meshrx.h); this package only marshals arguments.
 """
-from ._lib import MRX_TUNING_WIDE_LOOKBACK, MeshrxError, load, tunings  # noqa: F401
+from ._lib import MRX_TUNING_CLAIMED_TILES, MRX_TUNING_WIDE_LOOKBACK, MeshrxError, load, tunings  # noqa: F401
 
-__all__ = ["MRX_TUNING_WIDE_LOOKBACK", "MeshrxError", "load", "tunings", "reindex_mesh", "reindex_mesh_batched",
+__all__ = ["MRX_TUNING_CLAIMED_TILES", "MRX_TUNING_WIDE_LOOKBACK", "MeshrxError", "load", "tunings", "reindex_mesh", "reindex_mesh_batched",
            "gather_attrs", "GatherAttrs", "BatchedReindexer", "GraphedBatchedReindexer",
            "Reindexer", "workspace_size"]
 

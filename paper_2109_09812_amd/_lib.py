@@ -30,6 +30,7 @@ EXPORTS = (
 
 
 MRX_TUNING_WIDE_LOOKBACK = 1
+MRX_TUNING_CLAIMED_TILES = 2
 
 
 class Tuning(ctypes.Structure):

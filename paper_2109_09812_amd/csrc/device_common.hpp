@@ -189,9 +189,23 @@ __device__ __forceinline__ uint32_t lookback_exclusive(const uint64_t* base, int
   return lookback_finish<1, LbTagged>(win, base, stride, tag, ctl, status);
 }
 
-// Dynamic tile id: tiles are claimed in dispatch order, so every tile a
-// claimant waits on has already started.
+// Tile of this workgroup in a launch whose tiles wait on their predecessors
+// (decoupled look-back). Synchronises the block.
+//  * counter == nullptr: the workgroup id. A tile then only waits on tiles of
+//    smaller workgroup id; every die of the GPU dispatches its workgroups in
+//    increasing id order and runs them to completion, so the smallest
+//    unfinished tile is always running and the launch makes progress. No
+//    round trip precedes the tile's loads.
+//  * otherwise tiles are claimed from the counter in arrival order, so every
+//    tile a claimant waits on has already started, whatever the dispatch
+//    order; the claim's round trip delays every tile.
+// Either way the waits are bounded (kSpinLimit) and end in MRX_ERR_INTERNAL
+// rather than a hang.
 __device__ __forceinline__ uint32_t claim_tile(uint32_t* counter, uint32_t* s_slot) {
+  if (counter == nullptr) {
+    __syncthreads();
+    return blockIdx.x;
+  }
   if (threadIdx.x == 0) *s_slot = atomicAdd(counter, 1u);
   __syncthreads();
   uint32_t t = *s_slot;

@@ -131,7 +131,7 @@ bool wide_lookback(int64_t n, const mrx_tuning* t) {
 const SortVariant* pick_variant(int K, const mrx_tuning* t) {
   const auto& vs = variants_for(K);
   if (vs.empty()) return nullptr;
-  if (t && (t->flags & ~int32_t(MRX_TUNING_WIDE_LOOKBACK)) != 0) return nullptr;
+  if (t && (t->flags & ~int32_t(MRX_TUNING_WIDE_LOOKBACK | MRX_TUNING_CLAIMED_TILES)) != 0) return nullptr;
   if (!t || (t->digit_bits == 0 && t->block_threads == 0 && t->items_per_thread == 0)) return &vs[0];
   for (const auto& v : vs)
     if (v.D == t->digit_bits && v.block == t->block_threads && v.ipt == t->items_per_thread) return &v;
@@ -373,6 +373,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
   const bool wide = wide_lookback(n, tuning);
+  const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
   uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
                              reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
@@ -409,7 +410,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
       a.bucket_base = hist + size_t(p) * v.radix();
       a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
       a.lookback_next = lb32[(p + 1) & 1];
-      a.tile_counter = counters + p;
+      a.tile_counter = claimed ? counters + p : nullptr;
       a.ctl = ctl;
       a.status = status;
       a.n = n;
@@ -429,7 +430,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     f.rep = rep;
     f.used_g = used_g;
     f.lookback = scan_lookback;
-    f.tile_counter = counters + L.P_key;
+    f.tile_counter = claimed ? counters + L.P_key : nullptr;
     f.ctl = ctl;
     f.status = status;
     f.tag = uint32_t(L.P_key + 1);
@@ -447,7 +448,7 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
     c.out_num = out_num_vtx;
     c.cap = n;
     c.lookback = scan_lookback;
-    c.tile_counter = counters + L.P_key + 1;
+    c.tile_counter = claimed ? counters + L.P_key + 1 : nullptr;
     c.ctl = ctl;
     c.status = status;
     c.tag = uint32_t(L.P_key + 2);
@@ -506,6 +507,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
   const bool wide = wide_lookback(n, tuning);
+  const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
   uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
                              reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
@@ -543,7 +545,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
       a.bucket_base = hist + size_t(p) * v.radix();
       a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
       a.lookback_next = lb32[(p + 1) & 1];
-      a.tile_counter = counters + p;
+      a.tile_counter = claimed ? counters + p : nullptr;
       a.ctl = ctl;
       a.status = status;
       a.n = n;
@@ -571,7 +573,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     f.rep = rep;
     f.used_g = used_g;
     f.lookback = scan_lookback;
-    f.tile_counter = counters + P;
+    f.tile_counter = claimed ? counters + P : nullptr;
     f.ctl = ctl;
     f.status = status;
     f.mesh_off = vtx_offsets;
@@ -590,7 +592,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     c.out_num = &ctl->num_used;
     c.cap = n;
     c.lookback = scan_lookback;
-    c.tile_counter = counters + P + 1;
+    c.tile_counter = claimed ? counters + P + 1 : nullptr;
     c.ctl = ctl;
     c.status = status;
     c.tag = uint32_t(P + 2);

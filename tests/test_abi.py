@@ -117,7 +117,7 @@ def _call(**kw):
     (dict(out_idx=E), _lib.MRX_ERR_INVALID_ARGUMENT),          # out_idx == old2new
     (dict(new2old=W + 4096), _lib.MRX_ERR_INVALID_ARGUMENT),   # inside the workspace
     (dict(tuning=(10, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
-    (dict(tuning=(0, 0, 0, 2)), _lib.MRX_ERR_UNSUPPORTED),          # unknown flag bit
+    (dict(tuning=(0, 0, 0, 4)), _lib.MRX_ERR_UNSUPPORTED),          # unknown flag bit
     (dict(tuning=(8, 256, 16, 1 | 8)), _lib.MRX_ERR_UNSUPPORTED),
 ])
 def test_reindex_rejects_bad_arguments(kw, expected):
@@ -125,15 +125,18 @@ def test_reindex_rejects_bad_arguments(kw, expected):
 
 
 def test_tuning_flags():
-    # the wide look-back flag is accepted with the default or any compiled
-    # shape, and leaves the workspace size unchanged
+    # the flags are accepted with the default or any compiled shape and
+    # leave the workspace size unchanged
     st0, need0 = _ws(5000, 12, 3000)
     st1, need1 = _ws(5000, 12, 3000, tuning=(0, 0, 0, _lib.MRX_TUNING_WIDE_LOOKBACK))
     assert st0 == st1 == 0 and need0 == need1
+    both = _lib.MRX_TUNING_WIDE_LOOKBACK | _lib.MRX_TUNING_CLAIMED_TILES
     for t in _lib.tunings(12):
-        st, _ = _ws(5000, 12, 3000, tuning=(*t.as_tuple(), _lib.MRX_TUNING_WIDE_LOOKBACK))
-        assert st == 0, t.as_tuple()
+        for fl in (_lib.MRX_TUNING_WIDE_LOOKBACK, _lib.MRX_TUNING_CLAIMED_TILES, both):
+            st, need = _ws(5000, 12, 3000, tuning=(*t.as_tuple(), fl))
+            assert st == 0, (t.as_tuple(), fl)
     assert _ws(5000, 12, 3000, tuning=(0, 0, 0, 4))[0] == _lib.MRX_ERR_UNSUPPORTED
+    assert _ws(5000, 12, 3000, tuning=(0, 0, 0, both | 8))[0] == _lib.MRX_ERR_UNSUPPORTED
 
 
 def test_workspace_one_byte_short():

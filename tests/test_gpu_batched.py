@@ -130,11 +130,13 @@ def test_graph_replays_with_new_contents():
         _ = (tensors[0].float() * 2).sum().item()
 
 
-def test_batched_wide_lookback_words():
+def test_batched_tuning_flags():
     import paper_2109_09812_amd as mrx
     b = meshgen.batched(300, 100, 5000, 0.05, 616)
-    _say("batched wide look-back")
-    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, mrx.MRX_TUNING_WIDE_LOOKBACK)))
+    for fl in (mrx.MRX_TUNING_WIDE_LOOKBACK, mrx.MRX_TUNING_CLAIMED_TILES,
+               mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES):
+        _say("batched flags", fl)
+        check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, fl)))
 
 
 def test_batched_all_tunings_and_autotune(tmp_path):

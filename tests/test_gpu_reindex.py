@@ -161,20 +161,25 @@ def test_wide_records_all_tunings():
             assert np.array_equal(g, e)
 
 
-def test_wide_lookback_words_match():
-    """The 64-bit look-back words (forced here; automatic from 2^30 vertices
-    on) give the same result as the default 32-bit words, in every variant."""
+def test_tuning_flags_match():
+    """64-bit look-back words (forced here; automatic from 2^30 vertices on)
+    and counter-claimed tiles give the same result as the defaults, in every
+    variant."""
     import paper_2109_09812_amd as mrx
     m = meshgen.grid_soup(300, 0.07, 4321, "wide")
     exp = oracle.reindex(m.vtx, m.idx)
+    flag_sets = (mrx.MRX_TUNING_WIDE_LOOKBACK, mrx.MRX_TUNING_CLAIMED_TILES,
+                 mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES)
     for t in mrx.tunings(12):
-        shape = t.as_tuple()
-        _say("wide look-back", shape)
-        got = gpu(m.vtx, m.idx, tuning=(*shape, mrx.MRX_TUNING_WIDE_LOOKBACK))
-        for g, e in zip(got, exp):
-            assert np.array_equal(g, e)
-    assert_parity(*meshgen.random_mesh(70_001, 30_000, 3, 8, 9_000, 9191, 0.9),
-                  tuning=(0, 0, 0, mrx.MRX_TUNING_WIDE_LOOKBACK), name="wide K=8")
+        for fl in flag_sets:
+            shape = t.as_tuple()
+            _say("flags", fl, shape)
+            got = gpu(m.vtx, m.idx, tuning=(*shape, fl))
+            for g, e in zip(got, exp):
+                assert np.array_equal(g, e)
+    for fl in flag_sets:
+        assert_parity(*meshgen.random_mesh(70_001, 30_000, 3, 8, 9_000, 9191, 0.9),
+                      tuning=(0, 0, 0, fl), name=f"flags {fl} K=8")
 
 
 def test_tet_seam_does_not_merge():
