@@ -270,6 +270,46 @@ def bench_gather(args, torch, mrx, meshgen):
             "gather_bwd_ms": round(ms_b, 4), "gather_bwd_GBps": round(bwd_bytes / (ms_b * 1e-3) / 1e9, 1)}
 
 
+# The paper's Table 1 (RTX 3090, thrust + CUDA, end to end): quads per side ->
+# milliseconds. Context only: other hardware, 8-byte keys, transfers unstated.
+PAPER_GPU_MS = {1024: 9.2, 4096: 92.0, 8192: 338.0}
+
+
+def bench_configs(args, torch, mrx, meshgen):
+    """Re-index time of the other workloads (inputs resident in HBM, tuned
+    variant, mean over `steps` launches), each checked against its closed-form
+    output count."""
+    from paper_2109_09812_amd import autotune
+    dev = torch.device("cuda:0")
+    cases = [("soup256", meshgen.cfg1), ("tets64", meshgen.cfg3), ("soup10M", meshgen.cfg5_mesh)]
+    cases += [(f"paper_quads{q}", (lambda q=q: meshgen.paper_quads(q))) for q in (1024, 4096, 8192)]
+    out = {}
+    for name, make in cases:
+        m = make()
+        vtx = torch.from_numpy(m.vtx.view("int32")).to(dev)
+        idx = torch.from_numpy(m.idx).to(dev)
+        expected = m.expected_unique
+        del m
+        t, _ = autotune.autotune(vtx, idx, reps=2)
+        rx = mrx.Reindexer(vtx, idx, tuning=t)
+        rx.launch()
+        torch.cuda.synchronize()
+        ms, _ = timed_steps(rx.launch, args.steps, torch)
+        u = rx.result().num_out
+        n = vtx.shape[0]
+        row = {"num_vertices": n, "record_bytes": 4 * vtx.shape[1], "unique_out": u,
+               "closed_form_ok": u == expected, "ms": round(ms, 4),
+               "vertices_per_s": round(n / (ms * 1e-3)), "tuning": list(t.as_tuple())}
+        if name.startswith("paper_quads"):
+            q = int(name[len("paper_quads"):])
+            row["paper_rtx3090_ms"] = PAPER_GPU_MS[q]
+        out[name] = row
+        log(name, row)
+        del rx, vtx, idx
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(meshgen):
     """The oracle (serial std::map re-indexer) on the host, 1 thread, on a
     smaller soup of the same recipe, sized to ~10-20 s of work."""
@@ -326,6 +366,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gather", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' re-index times")
     ap.add_argument("--mode", choices=("full", "kernels"), default="full",
                     help="kernels: only the timed re-index steps and a 1 GiB copy probe (for profilers)")
     args = ap.parse_args()
@@ -353,6 +394,8 @@ def main():
     if not args.no_batched:
         extras["batched"] = bench_batched(args, torch, mrx, meshgen)
         log("batched", extras["batched"])
+    if not args.no_configs:
+        extras["other_workloads"] = bench_configs(args, torch, mrx, meshgen)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(meshgen)
