@@ -7,6 +7,13 @@ library and its Python binding) never imports, links or calls it.
 * ``reindex``            — serial std::map re-indexer (oracle.cpp), the plain
                            definition the GPU path must match bit for bit.
 * ``reindex_batched``    — the same, once per mesh of a packed batch.
+* ``merge``              — Section 3 "merging meshes": offset each mesh's local
+                           indices by its first vertex, then ``reindex`` the
+                           concatenation once (equal vertices of different
+                           meshes merge).
+* ``extract``            — Section 3 "computing a subset of a mesh": keep the
+                           flagged elements in order, then ``reindex`` (which
+                           drops the vertices only other elements used).
 * ``gather_attrs``       — torch CPU ``index_select`` (plus autograd for the
                            backward), the definition of the attribute gather.
 * ``paper_steps``        — a re-enactment of Section 2 Steps 1-4 in the
@@ -115,6 +122,39 @@ def reindex_batched(vtx, idx, vtx_offsets, elem_offsets):
     cat = lambda xs, shape: np.concatenate(xs) if xs else np.zeros(shape, np.int32)
     return (np.concatenate(outs_v) if outs_v else np.zeros((0, k), np.uint32), offs,
             cat(outs_i, (0, idx.shape[1])), cat(outs_o2n, (0,)), cat(outs_n2o, (0,)))
+
+
+def merge(vtx, idx, vtx_offsets, elem_offsets):
+    """Merge the meshes of a packed batch into one mesh (Section 3, "Merging
+    meshes that share (some) vertices"): the vertex arrays are already
+    concatenated; every mesh's local indices are raised by the number of
+    vertices of the meshes before it, and the single resulting mesh is
+    re-indexed. Returns ``reindex`` of it. A local index outside its own mesh
+    raises OracleIndexError with its position in the flat index array."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    arity = idx.shape[1]
+    gidx = np.empty(idx.shape, dtype=np.int64)
+    for b in range(len(vtx_offsets) - 1):
+        v0, v1 = int(vtx_offsets[b]), int(vtx_offsets[b + 1])
+        e0, e1 = int(elem_offsets[b]), int(elem_offsets[b + 1])
+        local = idx[e0:e1].astype(np.int64)
+        bad = np.flatnonzero(((local < 0) | (local >= v1 - v0)).reshape(-1))
+        if bad.size:
+            raise OracleIndexError(e0 * arity + int(bad[0]))
+        gidx[e0:e1] = local + v0
+    return reindex(vtx, gidx.astype(np.int32))
+
+
+def extract(vtx, idx, keep):
+    """Compact sub-mesh of the elements whose ``keep`` flag is set (Section 3,
+    "Computing a subset of a mesh"): the full vertex array with only those
+    elements, in their original order, re-indexed, so every vertex that only
+    dropped elements referenced disappears. Returns ``reindex`` of it
+    (out_idx has one row per kept element)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    keep = np.asarray(keep).astype(bool).reshape(-1)
+    assert keep.shape[0] == idx.shape[0]
+    return reindex(vtx, idx[keep])
 
 
 def gather_attrs(attrs, new2old):

@@ -299,6 +299,128 @@ def _pins_pass(lib_path):
         oracle._lib = saved
 
 
+# ----------------------------------------------------------------- merge (Section 3)
+
+def _merge_cases(count, seed=77):
+    """Tiny packed batches whose meshes draw records from one shared pool, so
+    equal vertices occur inside and across meshes."""
+    rng = np.random.default_rng(seed)
+    for c in range(count):
+        words = int(rng.integers(1, 4))
+        pool = rng.integers(0, 6, size=(int(rng.integers(1, 12)), words)).astype(np.uint32)
+        meshes = []
+        for _ in range(int(rng.integers(1, 5))):
+            n = int(rng.integers(0, 25))
+            e = int(rng.integers(0, 12)) if n else 0
+            v = pool[rng.integers(0, pool.shape[0], size=n)] if n else np.zeros((0, words), np.uint32)
+            i = rng.integers(0, n, size=(e, 3)).astype(np.int32) if e else np.zeros((0, 3), np.int32)
+            meshes.append((v, i))
+        vo = np.concatenate([[0], np.cumsum([m[0].shape[0] for m in meshes])]).astype(np.int64)
+        eo = np.concatenate([[0], np.cumsum([m[1].shape[0] for m in meshes])]).astype(np.int64)
+        vtx = np.concatenate([m[0] for m in meshes]).reshape(-1, words)
+        idx = np.concatenate([m[1] for m in meshes]).reshape(-1, 3)
+        yield meshes, vtx, idx, vo, eo
+
+
+def test_merge_matches_bruteforce_of_the_concatenation():
+    for meshes, vtx, idx, vo, eo in _merge_cases(120):
+        # global indices built element by element, independently of merge()
+        glob = []
+        base = 0
+        for v, i in meshes:
+            for row in i.tolist():
+                glob.append([x + base for x in row])
+            base += v.shape[0]
+        gidx = np.array(glob, dtype=np.int32).reshape(-1, 3)
+        got = oracle.merge(vtx, idx, vo, eo)
+        exp = bruteforce.reindex(vtx, gidx)
+        for x, y in zip(got, exp):
+            assert np.array_equal(x, y)
+
+
+def test_merge_of_copies_collapses_to_one_mesh():
+    m = meshgen.grid_soup(30, 0.1, 5, "copies")
+    single = oracle.reindex(m.vtx, m.idx)
+    b = 3
+    n, e = m.vtx.shape[0], m.idx.shape[0]
+    vtx = np.concatenate([m.vtx] * b)
+    idx = np.concatenate([m.idx] * b)
+    vo = np.arange(b + 1, dtype=np.int64) * n
+    eo = np.arange(b + 1, dtype=np.int64) * e
+    ov, oi, o2n, n2o = oracle.merge(vtx, idx, vo, eo)
+    assert np.array_equal(ov, single[0])
+    assert np.array_equal(n2o, single[3])           # representatives stay in copy 0
+    for c in range(b):
+        assert np.array_equal(oi[c * e:(c + 1) * e], single[1])
+        assert np.array_equal(o2n[c * n:(c + 1) * n], single[2])
+
+
+def test_merge_of_disjoint_meshes_adds_up():
+    parts = [meshgen.grid_soup(20 + 5 * s, 0.05, 60 + s, "part") for s in range(3)]
+    vs = []
+    for s, p in enumerate(parts):
+        v = p.vtx.copy()
+        v[:, 0] += np.float32(2 * s + 2)              # disjoint x ranges
+        vs.append(v)
+    vo = np.concatenate([[0], np.cumsum([v.shape[0] for v in vs])]).astype(np.int64)
+    eo = np.concatenate([[0], np.cumsum([p.idx.shape[0] for p in parts])]).astype(np.int64)
+    ov, oi, o2n, n2o = oracle.merge(np.concatenate(vs), np.concatenate([p.idx for p in parts]), vo, eo)
+    assert ov.shape[0] == sum(p.expected_unique for p in parts)
+
+
+def test_merge_checks_local_indices_per_mesh():
+    a = meshgen.grid_soup(10, 0.0, 1, "a")
+    b = meshgen.grid_soup(10, 0.0, 2, "b")
+    idx = np.concatenate([a.idx, b.idx]).copy()
+    e = a.idx.shape[0]
+    idx[e + 4, 2] = b.vtx.shape[0]            # a valid packed id, but outside mesh b
+    vo = np.array([0, a.vtx.shape[0], a.vtx.shape[0] + b.vtx.shape[0]], np.int64)
+    eo = np.array([0, e, e + b.idx.shape[0]], np.int64)
+    with pytest.raises(oracle.OracleIndexError) as ex:
+        oracle.merge(np.concatenate([a.vtx, b.vtx]), idx, vo, eo)
+    assert ex.value.pos == (e + 4) * 3 + 2
+    idx[e + 4, 2] = -1
+    with pytest.raises(oracle.OracleIndexError):
+        oracle.merge(np.concatenate([a.vtx, b.vtx]), idx, vo, eo)
+
+
+# ----------------------------------------------------------------- extract (Section 3)
+
+def test_extract_matches_bruteforce_of_kept_elements():
+    rng = np.random.default_rng(91)
+    for vtx, idx in _fuzz_cases(150):
+        keep = rng.random(idx.shape[0]) < rng.uniform(0, 1)
+        rows = [idx[r] for r in range(idx.shape[0]) if keep[r]]
+        kept = np.array(rows, dtype=np.int32).reshape(-1, idx.shape[1])
+        got = oracle.extract(vtx, idx, keep)
+        exp = bruteforce.reindex(vtx, kept)
+        for x, y in zip(got, exp):
+            assert np.array_equal(x, y)
+
+
+def test_extract_all_and_nothing():
+    m = meshgen.grid_soup(25, 0.1, 9, "ext")
+    full = oracle.reindex(m.vtx, m.idx)
+    got = oracle.extract(m.vtx, m.idx, np.ones(m.idx.shape[0], bool))
+    for x, y in zip(got, full):
+        assert np.array_equal(x, y)
+    ov, oi, o2n, n2o = oracle.extract(m.vtx, m.idx, np.zeros(m.idx.shape[0], bool))
+    assert ov.shape[0] == 0 and oi.shape == (0, 3) and n2o.size == 0 and np.all(o2n == -1)
+
+
+@pytest.mark.parametrize("n", [2, 8, 64])
+def test_extract_even_quad_rows_closed_form(n):
+    # quad e covers grid cells (e % n, e // n); rows 0, 2, .. n-2 use point rows 0 .. n-1
+    m = meshgen.paper_quads(n)
+    keep = (np.arange(n * n) // n) % 2 == 0
+    ov, oi, o2n, n2o = oracle.extract(m.vtx, m.idx, keep)
+    assert ov.shape[0] == n * (n + 1)
+    assert oi.shape == (n * n // 2, 4)
+    # copies of used values map, kept or not: all corners of kept rows and of
+    # the dropped rows between them, half the corners of the last (dropped) row
+    assert int((o2n >= 0).sum()) == 4 * n * n - 2 * n
+
+
 def test_oracle_mutants_are_caught(tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
