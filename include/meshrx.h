@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MRX_ABI_VERSION 1
+#define MRX_ABI_VERSION 2
 
 typedef enum {
   MRX_OK = 0,
@@ -95,10 +95,12 @@ int32_t mrx_tuning_count(int32_t vtx_bytes);
  * Variant 0 is the default. Returns MRX_ERR_INVALID_ARGUMENT otherwise. */
 mrx_status mrx_tuning_get(int32_t vtx_bytes, int32_t i, mrx_tuning* out);
 
-/* Bytes of device workspace needed by mrx_reindex_mesh (num_meshes == 1) or
- * mrx_reindex_mesh_batched (num_meshes >= 1) for these sizes and tuning
- * (NULL = default). num_idx = num_elems * arity. The workspace must be
- * 256-byte aligned; its contents need not be initialised and are clobbered. */
+/* Bytes of device workspace needed by mrx_reindex_mesh, mrx_merge_meshes and
+ * mrx_extract_submesh (num_meshes == 1; for a merge, num_vtx and num_idx are
+ * the batch totals) or mrx_reindex_mesh_batched (num_meshes >= 1) for these
+ * sizes and tuning (NULL = default). num_idx = num_elems * arity. The
+ * workspace must be 256-byte aligned; its contents need not be initialised
+ * and are clobbered. */
 mrx_status mrx_reindex_workspace_size(int64_t num_vtx, int32_t vtx_bytes, int64_t num_idx,
                                       int32_t num_meshes, const mrx_tuning* tuning,
                                       size_t* bytes);
@@ -157,6 +159,49 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
                                     int32_t* dev_status, void* workspace,
                                     size_t workspace_bytes, const mrx_tuning* tuning,
                                     void* stream);
+
+/* Merge num_meshes meshes into one (Section 3, "Merging meshes that share
+ * (some) vertices"): the packed vertex arrays are taken as one array, every
+ * mesh's local indices are raised by the mesh's first vertex, and the single
+ * mesh is re-indexed, so bitwise-equal vertices of different meshes merge.
+ *
+ *   vtx, vtx_offsets, idx, elem_offsets, total_*, arity, num_meshes: as for
+ *                 mrx_reindex_mesh_batched (idx MESH-LOCAL).
+ *   out_vtx       capacity total_vtx records; the first U are written.
+ *   out_idx       [total_elems * arity] int32, ids into out_vtx; may alias idx.
+ *   old2new       [total_vtx] int32, packed vertex id -> merged id (-1 unused).
+ *   new2old       capacity total_vtx int32 (packed vertex ids), or NULL.
+ *   out_num_vtx, dev_status, workspace (num_meshes == 1 sizing), tuning:
+ *                 as for mrx_reindex_mesh. A local index outside its own mesh
+ *                 is MRX_ERR_INDEX_OUT_OF_RANGE.
+ */
+mrx_status mrx_merge_meshes(const void* vtx, const int64_t* vtx_offsets, int64_t total_vtx,
+                            int32_t vtx_bytes, const int32_t* idx, const int64_t* elem_offsets,
+                            int64_t total_elems, int32_t arity, int32_t num_meshes,
+                            void* out_vtx, int32_t* out_idx, int32_t* old2new,
+                            int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status,
+                            void* workspace, size_t workspace_bytes,
+                            const mrx_tuning* tuning, void* stream);
+
+/* Compact sub-mesh of selected elements (Section 3, "Computing a subset of a
+ * mesh"): the elements e with keep[e] != 0 are kept in their order, the rest
+ * dropped, and the result re-indexed, so vertices only dropped elements used
+ * disappear.
+ *
+ *   vtx, num_vtx, vtx_bytes, idx, num_elems, arity: as for mrx_reindex_mesh.
+ *   keep           device uint8 [num_elems].
+ *   out_idx        capacity num_elems * arity int32; the first
+ *                  *out_num_elems elements are written. Must not overlap idx.
+ *   out_num_elems  device int64 scalar, receives the kept element count.
+ *   out_vtx, old2new (over all num_vtx input vertices), new2old, out_num_vtx,
+ *   dev_status, workspace, tuning: as for mrx_reindex_mesh.
+ */
+mrx_status mrx_extract_submesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
+                               const int32_t* idx, int64_t num_elems, int32_t arity,
+                               const uint8_t* keep, void* out_vtx, int32_t* out_idx,
+                               int64_t* out_num_elems, int32_t* old2new, int32_t* new2old,
+                               int64_t* out_num_vtx, int32_t* dev_status, void* workspace,
+                               size_t workspace_bytes, const mrx_tuning* tuning, void* stream);
 
 /* Per-vertex attributes of the re-indexed mesh: out[j, c] = attrs[new2old[j], c]
  * (Section 3 notes that vertices may carry attributes).

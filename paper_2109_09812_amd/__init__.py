@@ -7,14 +7,16 @@ include/meshrx.h); this package only marshals arguments.
 """
 from ._lib import MRX_TUNING_CLAIMED_TILES, MRX_TUNING_WIDE_LOOKBACK, MeshrxError, load, tunings  # noqa: F401
 
-__all__ = ["MRX_TUNING_CLAIMED_TILES", "MRX_TUNING_WIDE_LOOKBACK", "MeshrxError", "load", "tunings", "reindex_mesh", "reindex_mesh_batched",
+__all__ = ["MRX_TUNING_CLAIMED_TILES", "MRX_TUNING_WIDE_LOOKBACK", "MeshrxError", "load", "tunings",
+           "reindex_mesh", "reindex_mesh_batched", "merge_meshes", "extract_submesh",
            "gather_attrs", "GatherAttrs", "BatchedReindexer", "GraphedBatchedReindexer",
            "Reindexer", "workspace_size"]
 
 
 def __getattr__(name):
     # torch-dependent API is imported on first use
-    if name in ("reindex_mesh", "reindex_mesh_batched", "gather_attrs", "GatherAttrs",
+    if name in ("reindex_mesh", "reindex_mesh_batched", "merge_meshes", "extract_submesh", "Extracted",
+                "gather_attrs", "GatherAttrs",
                 "BatchedReindexer", "GraphedBatchedReindexer", "workspace_size", "Reindexed", "Reindexer",
                 "BatchReindexed"):
         from . import api

@@ -24,6 +24,7 @@ MRX_ERR_INTERNAL = 7
 EXPORTS = (
     "mrx_abi_version", "mrx_status_string", "mrx_tuning_count", "mrx_tuning_get",
     "mrx_reindex_workspace_size", "mrx_reindex_mesh", "mrx_reindex_mesh_batched",
+    "mrx_merge_meshes", "mrx_extract_submesh",
     "mrx_gather_attrs", "mrx_gather_attrs_backward",
     "mrx_profile_enable", "mrx_profile_count", "mrx_profile_get",
 )
@@ -58,6 +59,10 @@ _SIGS = {
                                 _vp, _sz, ctypes.POINTER(Tuning), _vp]),
     "mrx_reindex_mesh_batched": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(Tuning), _vp]),
+    "mrx_merge_meshes": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _sz, ctypes.POINTER(Tuning), _vp]),
+    "mrx_extract_submesh": (_i32, [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _sz, ctypes.POINTER(Tuning), _vp]),
     "mrx_gather_attrs": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _vp, _vp, _vp]),
     "mrx_gather_attrs_backward": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _vp, _i32, _vp, _vp]),
     "mrx_profile_enable": (_i32, [_i32]),

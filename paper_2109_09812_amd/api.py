@@ -53,7 +53,7 @@ class Reindexed:
 
     def trim(self) -> "Reindexed":
         """One device->host read of U and the status; raises on a data error."""
-        u, status = (int(x) for x in self.meta.cpu())
+        u, status = (int(x) for x in self.meta[:2].cpu())
         status &= 0xFFFFFFFF
         if status == MRX_ERR_INDEX_OUT_OF_RANGE:
             raise IndexError("an index entry is out of range")
@@ -91,6 +91,93 @@ def reindex_mesh(vtx: torch.Tensor, idx: torch.Tensor, *, tuning=None, workspace
         _ptr(workspace), workspace.numel(), make_tuning(tuning), ctypes.c_void_p(_stream_handle(dev)))
     check(st, "mrx_reindex_mesh")
     r = Reindexed(out_vtx, out_idx, old2new, new2old, meta)
+    return r.trim() if sync else r
+
+
+def _offsets_ok(o: torch.Tensor) -> bool:
+    return o.is_cuda and o.dtype == torch.int64 and o.dim() == 1 and o.is_contiguous()
+
+
+def merge_meshes(vtx: torch.Tensor, vtx_offsets: torch.Tensor, idx: torch.Tensor,
+                 elem_offsets: torch.Tensor, *, tuning=None, workspace=None, in_place: bool = False,
+                 want_new2old: bool = True, sync: bool = True) -> Reindexed:
+    """Merge the meshes of a packed batch into ONE mesh (Section 3, merging
+    meshes): mesh-local indices are offset by each mesh's first vertex and the
+    whole is re-indexed once, so bitwise-equal vertices of different meshes
+    merge. Returns out_vtx [U, K], out_idx [E, A] (ids into out_vtx),
+    old2new [N] over the packed vertices, new2old [U] (packed vertex ids)."""
+    _check_vtx(vtx)
+    _check_idx(idx)
+    if not (_offsets_ok(vtx_offsets) and _offsets_ok(elem_offsets)):
+        raise ValueError("offsets must be contiguous int64 device tensors")
+    if vtx_offsets.numel() != elem_offsets.numel() or vtx_offsets.numel() < 2:
+        raise ValueError("vtx_offsets and elem_offsets must both have num_meshes + 1 entries")
+    n, k = vtx.shape
+    dev = vtx.device
+    out_vtx = torch.empty_like(vtx)
+    out_idx = idx if in_place else torch.empty_like(idx)
+    old2new = torch.empty(n, dtype=torch.int32, device=dev)
+    new2old = torch.empty(n, dtype=torch.int32, device=dev) if want_new2old else None
+    meta = torch.zeros(2, dtype=torch.int64, device=dev)
+    wsb = workspace_size(n, 4 * k, idx.numel(), 1, tuning)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = load().mrx_merge_meshes(
+        _ptr(vtx), _ptr(vtx_offsets), n, 4 * k, _ptr(idx), _ptr(elem_offsets), idx.shape[0], idx.shape[1],
+        vtx_offsets.numel() - 1, _ptr(out_vtx), _ptr(out_idx), _ptr(old2new), _ptr(new2old), _ptr(meta),
+        ctypes.c_void_p(meta.data_ptr() + 8), _ptr(workspace), workspace.numel(), make_tuning(tuning),
+        ctypes.c_void_p(_stream_handle(dev)))
+    check(st, "mrx_merge_meshes")
+    r = Reindexed(out_vtx, out_idx, old2new, new2old, meta)
+    return r.trim() if sync else r
+
+
+@dataclasses.dataclass
+class Extracted(Reindexed):
+    """A Reindexed whose out_idx holds only the kept elements once trimmed;
+    meta[2] is the kept element count."""
+
+    num_elems_out: int | None = None
+
+    def trim(self) -> "Extracted":
+        super().trim()  # raises on a data error first
+        kept = int(self.meta[2].cpu())
+        self.num_elems_out = kept
+        self.out_idx = self.out_idx[:kept]
+        return self
+
+
+def extract_submesh(vtx: torch.Tensor, idx: torch.Tensor, keep: torch.Tensor, *, tuning=None,
+                    workspace=None, want_new2old: bool = True, sync: bool = True) -> Extracted:
+    """Compact sub-mesh of the elements with keep[e] set (Section 3, computing
+    a subset of a mesh): kept elements stay in order, vertices only dropped
+    elements used disappear. Returns out_vtx [U, K], out_idx [kept, A],
+    old2new [N] (over all input vertices), new2old [U]."""
+    _check_vtx(vtx)
+    _check_idx(idx)
+    if not keep.is_cuda or keep.dim() != 1 or keep.numel() != idx.shape[0] or not keep.is_contiguous():
+        raise ValueError("keep must be a contiguous [E] device tensor")
+    if keep.dtype == torch.bool:
+        keep = keep.view(torch.uint8)
+    elif keep.dtype != torch.uint8:
+        raise ValueError("keep must be bool or uint8")
+    n, k = vtx.shape
+    dev = vtx.device
+    out_vtx = torch.empty_like(vtx)
+    out_idx = torch.empty_like(idx)
+    old2new = torch.empty(n, dtype=torch.int32, device=dev)
+    new2old = torch.empty(n, dtype=torch.int32, device=dev) if want_new2old else None
+    meta = torch.zeros(3, dtype=torch.int64, device=dev)
+    wsb = workspace_size(n, 4 * k, idx.numel(), 1, tuning)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = load().mrx_extract_submesh(
+        _ptr(vtx), n, 4 * k, _ptr(idx), idx.shape[0], idx.shape[1], _ptr(keep), _ptr(out_vtx), _ptr(out_idx),
+        ctypes.c_void_p(meta.data_ptr() + 16), _ptr(old2new), _ptr(new2old), _ptr(meta),
+        ctypes.c_void_p(meta.data_ptr() + 8), _ptr(workspace), workspace.numel(), make_tuning(tuning),
+        ctypes.c_void_p(_stream_handle(dev)))
+    check(st, "mrx_extract_submesh")
+    r = Extracted(out_vtx, out_idx, old2new, new2old, meta)
     return r.trim() if sync else r
 
 

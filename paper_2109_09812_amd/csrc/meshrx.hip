@@ -10,19 +10,22 @@
 #include <vector>
 
 #include "../../include/meshrx.h"
+#include "edit_kernels.hpp"
 #include "registry.hpp"
 
 namespace mrx {
 
 // Zero a 16-byte aligned byte range (the per-call control state) and the
 // caller's status word.
-__global__ void k_fill_zero(uint4* __restrict__ p, int64_t n16, int32_t* status, int64_t* count) {
+__global__ void k_fill_zero(uint4* __restrict__ p, int64_t n16, int32_t* status, int64_t* count,
+                            int64_t* count2) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0, 0, 0, 0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (status) *status = 0;
     if (count) *count = 0;
+    if (count2) *count2 = 0;
   }
 }
 
@@ -148,12 +151,20 @@ struct Layout {
   int K = 0, S = 0, P_key = 0, P_mesh = 0;
   int64_t tiles_sort = 0, tiles_scan = 0;
   // zeroed region
-  size_t ctl = 0, counters = 0, hist = 0, lookback = 0, scan_lookback = 0, used_v = 0, used_g = 0, zero_end = 0;
+  size_t ctl = 0, counters = 0, hist = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0, used_v = 0,
+         used_g = 0, zero_end = 0;
+  int64_t tiles_elem = 0;
   // scratch
   size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, total = 0;
 };
 
-Layout make_layout(int64_t n, int K, int32_t nmesh, const SortVariant& v) {
+// Element tiles of the sub-mesh selection (k_select_elements).
+constexpr int kSelectBlock = 256;
+constexpr int kSelectIpt = 16;
+constexpr int kSelectTile = kSelectBlock * kSelectIpt;
+
+// num_idx bounds the element count of a sub-mesh selection (arity >= 1).
+Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortVariant& v) {
   Layout L;
   L.K = K;
   L.S = K + 1;
@@ -164,13 +175,15 @@ Layout make_layout(int64_t n, int K, int32_t nmesh, const SortVariant& v) {
   const int P = L.P_key + L.P_mesh;
   size_t off = 0;
   L.ctl = off;      off = align_up(off + sizeof(Control));
-  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + 2));
+  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + 3));
   L.hist = off;     off = align_up(off + sizeof(uint32_t) * size_t(P) * size_t(v.radix()));
   // sort look-back: tiles x radix 64-bit words, or two alternating buffers of
   // 32-bit words in the same bytes; flag scan and compaction have their own
   const int64_t lb_words = std::max<int64_t>(L.tiles_sort * v.radix(), 1);
   L.lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(lb_words));
   L.scan_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_scan + 1));
+  L.tiles_elem = (num_idx + kSelectTile - 1) / kSelectTile;
+  L.elem_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_elem + 1));
   L.used_v = off;   off = align_up(off + size_t(n));
   L.used_g = off;   off = align_up(off + size_t(n));
   L.zero_end = off;
@@ -255,6 +268,166 @@ mrx_status validate_common(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
 
 using namespace mrx;
 
+namespace mrx {
+namespace {
+
+// Checks shared by every single-mesh call; on success *layout describes the
+// workspace. `extra` lists caller buffers of the call that must not overlap
+// any of the others (NULL entries are ignored).
+mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, const int32_t* idx,
+                           int64_t num_elems, int32_t arity, const void* out_vtx, const int32_t* out_idx,
+                           const int32_t* old2new, const int32_t* new2old, const int64_t* out_num_vtx,
+                           const int32_t* dev_status, const void* workspace, size_t workspace_bytes,
+                           const mrx_tuning* tuning, std::initializer_list<Buffer> extra,
+                           const SortVariant** variant, Layout* layout) {
+  mrx_status st = validate_common(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx,
+                                  old2new, workspace, workspace_bytes);
+  if (st != MRX_OK) return st;
+  if (!out_num_vtx || !aligned(out_num_vtx, 8) || !aligned(new2old, 4) || !aligned(dev_status, 4))
+    return MRX_ERR_INVALID_ARGUMENT;
+  const int K = vtx_bytes / 4;
+  const SortVariant* vp = pick_variant(K, tuning);
+  if (!vp) return MRX_ERR_UNSUPPORTED;
+  const int64_t n = num_vtx, m = num_elems * arity;
+  const Layout L = make_layout(n, m, K, 1, *vp);
+  if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
+  const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4;
+  std::vector<Buffer> outs = {{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb},
+                              {new2old, new2old ? nb : 0}, {out_num_vtx, 8},
+                              {dev_status, dev_status ? 4u : 0u}, {workspace, L.total}};
+  for (const Buffer& b : extra) outs.push_back(b);
+  for (size_t i = 0; i < outs.size(); ++i)
+    for (size_t j = i + 1; j < outs.size(); ++j)
+      if (overlaps(outs[i].p, outs[i].bytes, outs[j].p, outs[j].bytes)) return MRX_ERR_INVALID_ARGUMENT;
+  // idx may be out_idx itself, but may not overlap any other buffer
+  if (idx != out_idx)
+    for (size_t j = 0; j < outs.size(); ++j)
+      if (overlaps(idx, ib, outs[j].p, outs[j].bytes)) return MRX_ERR_INVALID_ARGUMENT;
+  *variant = vp;
+  *layout = L;
+  return MRX_OK;
+}
+
+// The single-mesh launch sequence (Section 2, Steps 1-4). live_elems
+// (device, nullable) limits the index array to its first *live_elems
+// elements; num_elems is then only a capacity.
+mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx, int64_t num_vtx,
+                         int32_t vtx_bytes, const int32_t* idx, int64_t num_elems, int32_t arity,
+                         const int64_t* live_elems, void* out_vtx, int32_t* out_idx, int32_t* old2new,
+                         int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status, void* workspace,
+                         const mrx_tuning* tuning, void* stream_, bool state_zeroed = false) {
+  const int K = vtx_bytes / 4;
+  const int64_t n = num_vtx, m = num_elems * arity;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
+  const bool wide = wide_lookback(n, tuning);
+  const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
+  uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
+                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
+  uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
+  uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
+  uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
+  uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
+  int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
+  int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
+  int32_t* status = dev_status ? dev_status : &ctl->status;
+
+  // per-call state: look-back words, tile counters, histograms, flags, G
+  // (already cleared when a preceding step of the same call used it)
+  if (!state_zeroed) {
+    prof_mark("fill_zero", s);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
+                       static_cast<int64_t*>(nullptr));
+  }
+  // Step 1: mark referenced vertices (and report out-of-range entries)
+  if (m > 0) {
+    prof_mark("mark_used", s);
+    hipLaunchKernelGGL((k_mark_used<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
+                       nullptr, nullptr, 0, live_elems, used_v, status);
+  }
+  if (n > 0) {
+    // Step 2: stable LSD radix sort of (record, id | used << 31)
+    prof_mark("histogram", s);
+    v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    prof_mark("scan_buckets", s);
+    v.scan(hist, L.P_key, s);
+    const uint32_t* src = static_cast<const uint32_t*>(vtx);
+    int cur = 0;
+    for (int p = 0; p < L.P_key; ++p) {
+      SortPassArgs a{};
+      a.src = src;
+      a.dst = buf[cur];
+      a.used = used_v;
+      a.bucket_base = hist + size_t(p) * v.radix();
+      a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
+      a.lookback_next = lb32[(p + 1) & 1];
+      a.tile_counter = claimed ? counters + p : nullptr;
+      a.ctl = ctl;
+      a.status = status;
+      a.n = n;
+      set_digit(a, K, p * v.D);
+      a.tag = uint32_t(p + 1);
+      prof_mark(p == 0 ? "onesweep_first" : "onesweep", s);
+      v.pass(a, p == 0 ? kPassFirst : kPassKey, wide, L.tiles_sort, s);
+      src = buf[cur];
+      cur ^= 1;
+    }
+    // Step 2 flags + prefix sum, Step 3/4 scatters
+    FlagScanArgs f{};
+    f.sorted = src;
+    f.n = n;
+    f.pairs = reinterpret_cast<uint2*>(buf[cur]);  // the buffer the last pass read from
+    f.uniq = uniq;
+    f.rep = rep;
+    f.used_g = used_g;
+    f.lookback = scan_lookback;
+    f.tile_counter = claimed ? counters + L.P_key : nullptr;
+    f.ctl = ctl;
+    f.status = status;
+    f.tag = uint32_t(L.P_key + 1);
+    prof_mark("flag_scan", s);
+    v.flag_scan(f, false, L.tiles_scan, s);
+    // Step 3 on used groups only: compaction
+    CompactArgs c{};
+    c.used_g = used_g;
+    c.uniq = uniq;
+    c.rep = rep;
+    c.K = K;
+    c.out_vtx = static_cast<uint32_t*>(out_vtx);
+    c.new2old = new2old;
+    c.cmap = cmap;
+    c.out_num = out_num_vtx;
+    c.cap = n;
+    c.lookback = scan_lookback;
+    c.tile_counter = claimed ? counters + L.P_key + 1 : nullptr;
+    c.ctl = ctl;
+    c.status = status;
+    c.tag = uint32_t(L.P_key + 2);
+    prof_mark("compact", s);
+    hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
+    prof_mark("old2new", s);
+    hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
+                       f.pairs, cmap, n, nullptr, nullptr, 0, old2new);
+  }
+  // Step 4: remap the index array
+  if (m > 0) {
+    prof_mark("remap", s);
+    hipLaunchKernelGGL((k_remap<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
+                       nullptr, nullptr, 0, live_elems, old2new, out_idx);
+  }
+  prof_mark(nullptr, s);
+  return check_launch();
+}
+
+}  // namespace
+}  // namespace mrx
+
 extern "C" {
 
 int32_t mrx_abi_version(void) { return MRX_ABI_VERSION; }
@@ -336,136 +509,24 @@ mrx_status mrx_reindex_workspace_size(int64_t num_vtx, int32_t vtx_bytes, int64_
   if (num_vtx > kMaxCount || num_idx > kMaxCount) return MRX_ERR_TOO_LARGE;
   const SortVariant* v = pick_variant(vtx_bytes / 4, tuning);
   if (!v) return MRX_ERR_UNSUPPORTED;
-  *bytes = make_layout(num_vtx, vtx_bytes / 4, num_meshes, *v).total;
+  *bytes = make_layout(num_vtx, num_idx, vtx_bytes / 4, num_meshes, *v).total;
   return MRX_OK;
 }
+
 
 mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, const int32_t* idx,
                             int64_t num_elems, int32_t arity, void* out_vtx, int32_t* out_idx,
                             int32_t* old2new, int32_t* new2old, int64_t* out_num_vtx,
                             int32_t* dev_status, void* workspace, size_t workspace_bytes,
-                            const mrx_tuning* tuning, void* stream_) {
-  mrx_status st = validate_common(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx,
-                                  old2new, workspace, workspace_bytes);
+                            const mrx_tuning* tuning, void* stream) {
+  const SortVariant* v = nullptr;
+  Layout L;
+  mrx_status st = validate_single(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx, old2new,
+                                  new2old, out_num_vtx, dev_status, workspace, workspace_bytes, tuning, {},
+                                  &v, &L);
   if (st != MRX_OK) return st;
-  if (!out_num_vtx || !aligned(out_num_vtx, 8) || !aligned(new2old, 4) || !aligned(dev_status, 4))
-    return MRX_ERR_INVALID_ARGUMENT;
-  const int K = vtx_bytes / 4;
-  const SortVariant* vp = pick_variant(K, tuning);
-  if (!vp) return MRX_ERR_UNSUPPORTED;
-  const SortVariant& v = *vp;
-  const int64_t n = num_vtx, m = num_elems * arity;
-  const Layout L = make_layout(n, K, 1, v);
-  if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
-  const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4;
-  if (!disjoint({{vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
-                 {out_num_vtx, 8}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
-                 {idx == out_idx ? nullptr : idx, ib}}) ||
-      !disjoint({{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
-                 {out_num_vtx, 8}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total}}))
-    return MRX_ERR_INVALID_ARGUMENT;
-
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
-  char* ws = static_cast<char*>(workspace);
-  Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
-  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
-  uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
-  uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
-  const bool wide = wide_lookback(n, tuning);
-  const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
-  uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
-                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
-  uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
-  uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
-  uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b)};
-  uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
-  int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
-  int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
-  int32_t* status = dev_status ? dev_status : &ctl->status;
-
-  // per-call state: look-back words, tile counters, histograms, flags, G
-  prof_mark("fill_zero", s);
-  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
-                     reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx);
-  // Step 1: mark referenced vertices (and report out-of-range entries)
-  if (m > 0) {
-    prof_mark("mark_used", s);
-    hipLaunchKernelGGL((k_mark_used<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       nullptr, nullptr, 0, used_v, status);
-  }
-  if (n > 0) {
-    // Step 2: stable LSD radix sort of (record, id | used << 31)
-    prof_mark("histogram", s);
-    v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
-    prof_mark("scan_buckets", s);
-    v.scan(hist, L.P_key, s);
-    const uint32_t* src = static_cast<const uint32_t*>(vtx);
-    int cur = 0;
-    for (int p = 0; p < L.P_key; ++p) {
-      SortPassArgs a{};
-      a.src = src;
-      a.dst = buf[cur];
-      a.used = used_v;
-      a.bucket_base = hist + size_t(p) * v.radix();
-      a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
-      a.lookback_next = lb32[(p + 1) & 1];
-      a.tile_counter = claimed ? counters + p : nullptr;
-      a.ctl = ctl;
-      a.status = status;
-      a.n = n;
-      set_digit(a, K, p * v.D);
-      a.tag = uint32_t(p + 1);
-      prof_mark(p == 0 ? "onesweep_first" : "onesweep", s);
-      v.pass(a, p == 0 ? kPassFirst : kPassKey, wide, L.tiles_sort, s);
-      src = buf[cur];
-      cur ^= 1;
-    }
-    // Step 2 flags + prefix sum, Step 3/4 scatters
-    FlagScanArgs f{};
-    f.sorted = src;
-    f.n = n;
-    f.pairs = reinterpret_cast<uint2*>(buf[cur]);  // the buffer the last pass read from
-    f.uniq = uniq;
-    f.rep = rep;
-    f.used_g = used_g;
-    f.lookback = scan_lookback;
-    f.tile_counter = claimed ? counters + L.P_key : nullptr;
-    f.ctl = ctl;
-    f.status = status;
-    f.tag = uint32_t(L.P_key + 1);
-    prof_mark("flag_scan", s);
-    v.flag_scan(f, false, L.tiles_scan, s);
-    // Step 3 on used groups only: compaction
-    CompactArgs c{};
-    c.used_g = used_g;
-    c.uniq = uniq;
-    c.rep = rep;
-    c.K = K;
-    c.out_vtx = static_cast<uint32_t*>(out_vtx);
-    c.new2old = new2old;
-    c.cmap = cmap;
-    c.out_num = out_num_vtx;
-    c.cap = n;
-    c.lookback = scan_lookback;
-    c.tile_counter = claimed ? counters + L.P_key + 1 : nullptr;
-    c.ctl = ctl;
-    c.status = status;
-    c.tag = uint32_t(L.P_key + 2);
-    prof_mark("compact", s);
-    hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
-    prof_mark("old2new", s);
-    hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       f.pairs, cmap, n, nullptr, nullptr, 0, old2new);
-  }
-  // Step 4: remap the index array
-  if (m > 0) {
-    prof_mark("remap", s);
-    hipLaunchKernelGGL((k_remap<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       nullptr, nullptr, 0, old2new, out_idx);
-  }
-  prof_mark(nullptr, s);
-  return check_launch();
+  return launch_single(*v, L, vtx, num_vtx, vtx_bytes, idx, num_elems, arity, nullptr, out_vtx, out_idx,
+                       old2new, new2old, out_num_vtx, dev_status, workspace, tuning, stream);
 }
 
 mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets, int64_t total_vtx,
@@ -487,7 +548,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   if (!vp) return MRX_ERR_UNSUPPORTED;
   const SortVariant& v = *vp;
   const int64_t n = total_vtx, m = total_elems * arity;
-  const Layout L = make_layout(n, K, num_meshes, v);
+  const Layout L = make_layout(n, m, K, num_meshes, v);
   if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
   const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4,
                ob = size_t(num_meshes + 1) * 8;
@@ -522,11 +583,12 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   prof_mark("fill_zero", s);
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status,
-                     static_cast<int64_t*>(nullptr));
+                     static_cast<int64_t*>(nullptr), static_cast<int64_t*>(nullptr));
   if (m > 0) {
     prof_mark("mark_used", s);
     hipLaunchKernelGGL((k_mark_used<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       vtx_offsets, elem_offsets, num_meshes, used_v, status);
+                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int64_t*>(nullptr), used_v,
+                       status);
   }
   if (n > 0) {
     prof_mark("histogram", s);
@@ -621,10 +683,85 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   if (m > 0) {
     prof_mark("remap", s);
     hipLaunchKernelGGL((k_remap<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       vtx_offsets, elem_offsets, num_meshes, old2new, out_idx);
+                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int64_t*>(nullptr), old2new,
+                       out_idx);
   }
   prof_mark(nullptr, s);
   return check_launch();
+}
+
+mrx_status mrx_merge_meshes(const void* vtx, const int64_t* vtx_offsets, int64_t total_vtx, int32_t vtx_bytes,
+                            const int32_t* idx, const int64_t* elem_offsets, int64_t total_elems,
+                            int32_t arity, int32_t num_meshes, void* out_vtx, int32_t* out_idx,
+                            int32_t* old2new, int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status,
+                            void* workspace, size_t workspace_bytes, const mrx_tuning* tuning,
+                            void* stream) {
+  if (num_meshes < 1 || !vtx_offsets || !elem_offsets || !aligned(vtx_offsets, 8) ||
+      !aligned(elem_offsets, 8))
+    return MRX_ERR_INVALID_ARGUMENT;
+  const size_t ob = sizeof(int64_t) * (size_t(num_meshes) + 1);
+  const SortVariant* v = nullptr;
+  Layout L;
+  mrx_status st = validate_single(vtx, total_vtx, vtx_bytes, idx, total_elems, arity, out_vtx, out_idx,
+                                  old2new, new2old, out_num_vtx, dev_status, workspace, workspace_bytes,
+                                  tuning, {{vtx_offsets, ob}, {elem_offsets, ob}}, &v, &L);
+  if (st != MRX_OK) return st;
+  // the offsets must not overlap each other either
+  if (overlaps(vtx_offsets, ob, elem_offsets, ob)) return MRX_ERR_INVALID_ARGUMENT;
+  const int64_t m = total_elems * arity;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (m > 0) {
+    prof_mark("offset_indices", s);
+    hipLaunchKernelGGL(k_offset_indices, dim3((m + 255) / 256), dim3(256), 0, s, idx, m, arity, vtx_offsets,
+                       elem_offsets, num_meshes, out_idx);
+  }
+  return launch_single(*v, L, vtx, total_vtx, vtx_bytes, out_idx, total_elems, arity, nullptr, out_vtx,
+                       out_idx, old2new, new2old, out_num_vtx, dev_status, workspace, tuning, stream);
+}
+
+mrx_status mrx_extract_submesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, const int32_t* idx,
+                               int64_t num_elems, int32_t arity, const uint8_t* keep, void* out_vtx,
+                               int32_t* out_idx, int64_t* out_num_elems, int32_t* old2new, int32_t* new2old,
+                               int64_t* out_num_vtx, int32_t* dev_status, void* workspace,
+                               size_t workspace_bytes, const mrx_tuning* tuning, void* stream) {
+  if (!out_num_elems || !aligned(out_num_elems, 8)) return MRX_ERR_INVALID_ARGUMENT;
+  if (num_elems > 0 && (!keep || idx == out_idx)) return MRX_ERR_INVALID_ARGUMENT;
+  const SortVariant* v = nullptr;
+  Layout L;
+  mrx_status st = validate_single(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx, old2new,
+                                  new2old, out_num_vtx, dev_status, workspace, workspace_bytes, tuning,
+                                  {{keep, size_t(num_elems)}, {out_num_elems, 8}}, &v, &L);
+  if (st != MRX_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
+  // per-call state for the selection and the re-index that follows it
+  prof_mark("fill_zero", s);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
+                     out_num_elems);
+  if (num_elems > 0) {
+    SelectArgs a{};
+    a.keep = keep;
+    a.idx = idx;
+    a.num_elems = num_elems;
+    a.arity = arity;
+    a.out = out_idx;
+    a.out_count = out_num_elems;
+    a.lookback = reinterpret_cast<uint64_t*>(ws + L.elem_lookback);
+    a.tile_counter = (tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES))
+                         ? reinterpret_cast<uint32_t*>(ws + L.counters) + L.P_key + L.P_mesh + 2
+                         : nullptr;
+    a.ctl = ctl;
+    a.status = dev_status ? dev_status : &ctl->status;
+    a.tag = 1;
+    const int64_t tiles = (num_elems + kSelectTile - 1) / kSelectTile;
+    prof_mark("select_elements", s);
+    hipLaunchKernelGGL((k_select_elements<kSelectBlock, kSelectIpt>), dim3(tiles), dim3(kSelectBlock), 0, s, a);
+  }
+  return launch_single(*v, L, vtx, num_vtx, vtx_bytes, out_idx, num_elems, arity, out_num_elems, out_vtx,
+                       out_idx, old2new, new2old, out_num_vtx, dev_status, workspace, tuning, stream,
+                       /*state_zeroed=*/true);
 }
 
 }  // extern "C"

@@ -25,8 +25,11 @@ __global__ __launch_bounds__(kRandBlock) void k_mark_used(const int32_t* __restr
                                                           int32_t arity, int64_t n,
                                                           const int64_t* __restrict__ vtx_off,
                                                           const int64_t* __restrict__ elem_off,
-                                                          int32_t nmesh, uint8_t* __restrict__ used,
-                                                          int32_t* status) {
+                                                          int32_t nmesh,
+                                                          const int64_t* __restrict__ live_elems,
+                                                          uint8_t* __restrict__ used, int32_t* status) {
+  // live_elems (device, nullable): only the first *live_elems elements count
+  if (live_elems) m = min(m, *live_elems * arity);
   const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
   int32_t v[kRandItems];
 #pragma unroll
@@ -315,7 +318,9 @@ template <bool BATCHED>
 __global__ __launch_bounds__(kRandBlock) void k_remap(const int32_t* idx, int64_t m, int32_t arity, int64_t n,
                                                       const int64_t* __restrict__ vtx_off,
                                                       const int64_t* __restrict__ elem_off, int32_t nmesh,
+                                                      const int64_t* __restrict__ live_elems,
                                                       const int32_t* __restrict__ old2new, int32_t* out_idx) {
+  if (live_elems) m = min(m, *live_elems * arity);  // see k_mark_used
   const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
   int64_t src[kRandItems];
 #pragma unroll

@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     lib = _lib.load()
-    assert lib.mrx_abi_version() == 1
+    assert lib.mrx_abi_version() == 2
     for code, name in [(0, "MRX_OK"), (1, "MRX_ERR_INVALID_ARGUMENT"), (2, "MRX_ERR_WORKSPACE_TOO_SMALL"),
                        (3, "MRX_ERR_INDEX_OUT_OF_RANGE"), (4, "MRX_ERR_TOO_LARGE"), (5, "MRX_ERR_HIP"),
                        (6, "MRX_ERR_UNSUPPORTED"), (7, "MRX_ERR_INTERNAL")]:
@@ -116,6 +116,7 @@ def _call(**kw):
     (dict(old2new=C + 8), _lib.MRX_ERR_INVALID_ARGUMENT),      # overlaps out_vtx
     (dict(out_idx=E), _lib.MRX_ERR_INVALID_ARGUMENT),          # out_idx == old2new
     (dict(new2old=W + 4096), _lib.MRX_ERR_INVALID_ARGUMENT),   # inside the workspace
+    (dict(out_idx=B + 4), _lib.MRX_ERR_INVALID_ARGUMENT),        # overlaps idx without being it
     (dict(tuning=(10, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
     (dict(tuning=(0, 0, 0, 4)), _lib.MRX_ERR_UNSUPPORTED),          # unknown flag bit
     (dict(tuning=(8, 256, 16, 1 | 8)), _lib.MRX_ERR_UNSUPPORTED),
@@ -156,6 +157,45 @@ def test_batched_rejects_bad_arguments():
     bad = list(base); bad[10] = 0x7E200004
     assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # misaligned offsets
     bad = list(base); bad[16] = 256
+    assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_merge_rejects_bad_arguments():
+    f = _lib.load().mrx_merge_meshes
+    # vtx, vtx_off, total_vtx, vb, idx, elem_off, total_elems, arity, meshes, out_vtx, out_idx,
+    # old2new, new2old, out_num, status, ws, wsb, tuning, stream
+    base = [A, 0x7E000000, 100, 12, B, 0x7E100000, 10, 3, 4, C, D, E, F, 0x7F000000, 0x7F000100, W,
+            1 << 30, None, None]
+    assert f(*base[:8], 0, *base[9:]) == _lib.MRX_ERR_INVALID_ARGUMENT          # no meshes
+    bad = list(base); bad[5] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no elem_offsets
+    bad = list(base); bad[5] = 0x7E000008
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # offsets overlap
+    bad = list(base); bad[13] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no out_num_vtx
+    bad = list(base); bad[16] = 256
+    assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
+    bad = list(base); bad[17] = _lib.make_tuning((0, 0, 0, 4))
+    assert f(*bad) == _lib.MRX_ERR_UNSUPPORTED
+
+
+def test_extract_rejects_bad_arguments():
+    f = _lib.load().mrx_extract_submesh
+    # vtx, n, vb, idx, ne, arity, keep, out_vtx, out_idx, out_num_elems, old2new, new2old, out_num,
+    # status, ws, wsb, tuning, stream
+    base = [A, 100, 12, B, 10, 3, 0x7E000000, C, D, 0x7E100000, E, F, 0x7F000000, 0x7F000100, W, 1 << 30,
+            None, None]
+    bad = list(base); bad[6] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no keep flags
+    bad = list(base); bad[8] = B
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # out_idx is idx
+    bad = list(base); bad[9] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no kept count
+    bad = list(base); bad[9] = 0x7E100004
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # misaligned count
+    bad = list(base); bad[6] = D + 8
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # keep overlaps out_idx
+    bad = list(base); bad[15] = 256
     assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
 
 
