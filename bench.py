@@ -23,6 +23,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -137,6 +139,7 @@ def bench_single(args, torch, mrx, meshgen):
     check_properties(m.vtx, m.idx, res.out_vtx.cpu().numpy().view("uint32"), res.out_idx.cpu().numpy(),
                      res.old2new.cpu().numpy(), res.new2old.cpu().numpy(), expected_unique=2048 * 2048)
     log(f"verified ({time.perf_counter() - t0:.1f}s): U={u}")
+    extract = bench_extract(args, torch, mrx, m, vtx, idx, u)
 
     passes = table.get("onesweep", (0, 0.0))
     s_elem = r_bytes + 4
@@ -156,7 +159,7 @@ def bench_single(args, torch, mrx, meshgen):
     for name, b in model.items():
         if name in kernels and table[name][1] > 0:
             kernels[name]["model_GBps"] = round(b / (table[name][1] * 1e-3) / 1e9, 1)
-    return dict(n=n, m=e * a, u=u, ms=ms, ms_prof=ms_prof, kernels=kernels,
+    return dict(n=n, m=e * a, u=u, ms=ms, ms_prof=ms_prof, kernels=kernels, extract=extract,
                 roofline_pass=dict(achieved=achieved, bytes=pass_bytes, mean_ms=passes[1]),
                 step_model_bytes_sort=step_bytes, r_bytes=r_bytes)
 
@@ -220,12 +223,73 @@ def bench_batched(args, torch, mrx, meshgen):
             torch.equal(counts, res.out_vtx_offsets[1:] - res.out_vtx_offsets[:-1]) and
             int(status.abs().sum()) == 0)
     exp_ok = bool((torch.diff(res.out_vtx_offsets).cpu().numpy() == b.expected_unique).all())
+    del g, res, out_vtx, out_idx, o2n, n2o, ws
+    torch.cuda.empty_cache()
+    merge = bench_merge(args, torch, mrx, b, vtx, vo, idx, eo)
     return {"workload": "batch4096: 4096 soups, log-uniform [100, 200000] triangles, 5% unused",
             "total_vertices": n, "batched_ms": round(ms_b, 3), "per_mesh_ms": round(ms_p, 3),
             "batched_vertices_per_s": n / (ms_b * 1e-3), "per_mesh_vertices_per_s": n / (ms_p * 1e-3),
             "speedup": round(ms_p / ms_b, 2), "batched_equals_per_mesh": bool(same),
             "tuning": list(t.as_tuple()),
-            "closed_form_counts_ok": exp_ok}
+            "closed_form_counts_ok": exp_ok, "merge": merge}
+
+
+def _sampled_records_ok(vtx_np, src_rows, out_idx, out_vtx, new2old, rng, count=20000):
+    """For sampled index entries: the output vertex an entry points to holds
+    the bytes of the input vertex it pointed to, and so does its
+    representative."""
+    import torch
+    flat_src = src_rows.reshape(-1)
+    k = rng.integers(0, flat_src.size, size=min(count, flat_src.size))
+    kk = torch.from_numpy(k).to(out_idx.device)
+    u = out_idx.reshape(-1)[kk].long()
+    ov = out_vtx[u].cpu().numpy().view(np.uint32)
+    rep = new2old[u].cpu().numpy()
+    src = vtx_np.view(np.uint32)[flat_src[k]]
+    return bool(np.array_equal(ov, src) and np.array_equal(vtx_np.view(np.uint32)[rep], src))
+
+
+def bench_extract(args, torch, mrx, mesh, vtx, idx, u_full):
+    """Section 3 sub-mesh of half of soup2048's triangles (seeded random)."""
+    keep_np = np.random.default_rng(2109).random(idx.shape[0]) < 0.5
+    keep = torch.from_numpy(keep_np).to(vtx.device)
+    x = mrx.SubmeshExtractor(vtx, idx, keep)
+    x.launch()
+    torch.cuda.synchronize()
+    ms, _ = timed_steps(x.launch, max(1, min(args.steps, 10)), torch)
+    r = x.result()
+    ok = _sampled_records_ok(mesh.vtx, mesh.idx[keep_np], r.out_idx, r.out_vtx, r.new2old,
+                             np.random.default_rng(8))
+    n = vtx.shape[0]
+    out = {"workload": "soup2048, half of the triangles kept (seeded random)", "ms": round(ms, 3),
+           "vertices_per_s": n / (ms * 1e-3), "kept_elements": r.num_elems_out,
+           "kept_elements_ok": r.num_elems_out == int(keep_np.sum()), "unique_out": r.num_out,
+           "fewer_than_full": bool(r.num_out < u_full), "sampled_records_ok": ok}
+    log("extract", out)
+    del x, r
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_merge(args, torch, mrx, b, vtx, vo, idx, eo):
+    """Section 3 merge of the whole batch4096 into one mesh."""
+    m = mrx.MeshMerger(vtx, vo, idx, eo)
+    m.launch()
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 5))
+    ms, _ = timed_steps(m.launch, reps, torch)
+    r = m.result()
+    mesh_of_elem = np.repeat(np.arange(b.num_meshes), np.diff(b.elem_offsets))
+    glob = b.idx.astype(np.int64) + b.vtx_offsets[mesh_of_elem][:, None]
+    ok = _sampled_records_ok(b.vtx, glob, r.out_idx, r.out_vtx, r.new2old, np.random.default_rng(7))
+    n = vtx.shape[0]
+    out = {"workload": "batch4096 merged into one mesh", "ms": round(ms, 3),
+           "vertices_per_s": n / (ms * 1e-3), "unique_out": r.num_out,
+           "fewer_than_per_mesh": bool(r.num_out < int(b.expected_unique.sum())), "sampled_records_ok": ok}
+    log("merge", out)
+    del m, r
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_gather(args, torch, mrx, meshgen):
@@ -430,6 +494,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": single["kernels"],
         "ms_per_step_profiled": round(single["ms_prof"], 5),
+        "extract": single["extract"],
     }
     line.update(extras)
     print(json.dumps(line))

@@ -181,6 +181,80 @@ def extract_submesh(vtx: torch.Tensor, idx: torch.Tensor, keep: torch.Tensor, *,
     return r.trim() if sync else r
 
 
+class MeshMerger:
+    """Preallocated merge of a packed batch of fixed shape (see
+    merge_meshes); ``launch()`` enqueues it without allocating or
+    synchronising."""
+
+    def __init__(self, vtx, vtx_offsets, idx, elem_offsets, *, tuning=None, want_new2old: bool = True):
+        _check_vtx(vtx)
+        _check_idx(idx)
+        if not (_offsets_ok(vtx_offsets) and _offsets_ok(elem_offsets)) or \
+                vtx_offsets.numel() != elem_offsets.numel() or vtx_offsets.numel() < 2:
+            raise ValueError("offsets must be contiguous int64 device tensors of num_meshes + 1 entries")
+        self.vtx, self.vtx_offsets, self.idx, self.elem_offsets = vtx, vtx_offsets, idx, elem_offsets
+        n, k = vtx.shape
+        dev = vtx.device
+        self.out_vtx = torch.empty_like(vtx)
+        self.out_idx = torch.empty_like(idx)
+        self.old2new = torch.empty(n, dtype=torch.int32, device=dev)
+        self.new2old = torch.empty(n, dtype=torch.int32, device=dev) if want_new2old else None
+        self.meta = torch.zeros(2, dtype=torch.int64, device=dev)
+        wsb = workspace_size(n, 4 * k, idx.numel(), 1, tuning)
+        self.workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+        self._tuning_ptr = make_tuning(tuning)
+
+    def launch(self):
+        n, k = self.vtx.shape
+        st = load().mrx_merge_meshes(
+            _ptr(self.vtx), _ptr(self.vtx_offsets), n, 4 * k, _ptr(self.idx), _ptr(self.elem_offsets),
+            self.idx.shape[0], self.idx.shape[1], self.vtx_offsets.numel() - 1, _ptr(self.out_vtx),
+            _ptr(self.out_idx), _ptr(self.old2new), _ptr(self.new2old), _ptr(self.meta),
+            ctypes.c_void_p(self.meta.data_ptr() + 8), _ptr(self.workspace), self.workspace.numel(),
+            self._tuning_ptr, ctypes.c_void_p(_stream_handle(self.vtx.device)))
+        check(st, "mrx_merge_meshes")
+
+    def result(self) -> Reindexed:
+        return Reindexed(self.out_vtx, self.out_idx, self.old2new, self.new2old, self.meta).trim()
+
+
+class SubmeshExtractor:
+    """Preallocated sub-mesh extraction for a fixed mesh shape (see
+    extract_submesh); refill ``keep`` in place between launches."""
+
+    def __init__(self, vtx, idx, keep, *, tuning=None, want_new2old: bool = True):
+        _check_vtx(vtx)
+        _check_idx(idx)
+        if not keep.is_cuda or keep.dim() != 1 or keep.numel() != idx.shape[0] or not keep.is_contiguous() \
+                or keep.dtype not in (torch.bool, torch.uint8):
+            raise ValueError("keep must be a contiguous [E] bool/uint8 device tensor")
+        self.vtx, self.idx = vtx, idx
+        self.keep = keep.view(torch.uint8) if keep.dtype == torch.bool else keep
+        n, k = vtx.shape
+        dev = vtx.device
+        self.out_vtx = torch.empty_like(vtx)
+        self.out_idx = torch.empty_like(idx)
+        self.old2new = torch.empty(n, dtype=torch.int32, device=dev)
+        self.new2old = torch.empty(n, dtype=torch.int32, device=dev) if want_new2old else None
+        self.meta = torch.zeros(3, dtype=torch.int64, device=dev)
+        wsb = workspace_size(n, 4 * k, idx.numel(), 1, tuning)
+        self.workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+        self._tuning_ptr = make_tuning(tuning)
+
+    def launch(self):
+        n, k = self.vtx.shape
+        st = load().mrx_extract_submesh(
+            _ptr(self.vtx), n, 4 * k, _ptr(self.idx), self.idx.shape[0], self.idx.shape[1], _ptr(self.keep),
+            _ptr(self.out_vtx), _ptr(self.out_idx), ctypes.c_void_p(self.meta.data_ptr() + 16),
+            _ptr(self.old2new), _ptr(self.new2old), _ptr(self.meta), ctypes.c_void_p(self.meta.data_ptr() + 8),
+            _ptr(self.workspace), self.workspace.numel(), self._tuning_ptr,
+            ctypes.c_void_p(_stream_handle(self.vtx.device)))
+        check(st, "mrx_extract_submesh")
+
+    def result(self) -> "Extracted":
+        return Extracted(self.out_vtx, self.out_idx, self.old2new, self.new2old, self.meta).trim()
+
+
 class Reindexer:
     """Preallocated outputs and workspace for one mesh shape; ``launch()``
     enqueues the whole re-index on the current stream without allocating or

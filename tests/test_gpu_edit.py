@@ -171,3 +171,30 @@ def test_extract_all_tunings_and_flags():
         for fl in (0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES):
             _say("extract tuning", t.as_tuple(), fl)
             _same(_extract(m.vtx, m.idx, keep, tuning=(*t.as_tuple(), fl)), exp, "extract tuning")
+
+
+def test_preallocated_merger_and_extractor_relaunch():
+    """The preallocated classes launch repeatedly; the extractor's keep flags
+    are refilled in place between launches."""
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(30, 100, 3000, 0.05, 444)
+    mg = mrx.MeshMerger(*_dev_batch(b))
+    exp = oracle.merge(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
+    for rep in range(2):
+        _say("merger launch", rep)
+        mg.launch()
+        _same(_host(mg.result()), exp, "merger")
+    m = meshgen.grid_soup(150, 0.05, 45, "relaunch")
+    v = torch.from_numpy(np.ascontiguousarray(m.vtx).view(np.int32)).to(DEV)
+    i = torch.from_numpy(m.idx).to(DEV)
+    keep = torch.zeros(m.idx.shape[0], dtype=torch.bool, device=DEV)
+    x = mrx.SubmeshExtractor(v, i, keep)
+    rng = np.random.default_rng(46)
+    for rep, frac in enumerate((0.7, 0.2, 0.0)):
+        k = rng.random(m.idx.shape[0]) < frac
+        keep.copy_(torch.from_numpy(k))
+        _say("extractor launch", rep, frac)
+        x.launch()
+        r = x.result()
+        assert r.num_elems_out == int(k.sum())
+        _same(_host(r), oracle.extract(m.vtx, m.idx, k), f"extractor{rep}")
