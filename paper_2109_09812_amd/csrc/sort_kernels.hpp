@@ -240,6 +240,38 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // ---- load
   uint32_t v[IPT][S];
   const int64_t wave_base = tile_base + int64_t(wave) * (kWave * IPT) + lane;
+
+  // First pass: the referenced flags of the wave's kWave*IPT consecutive
+  // vertices are read as whole words (lane i takes bytes [i*IPT, i*IPT+IPT)
+  // of the chunk) and handed to the lanes that own them through LDS, instead
+  // of one byte load per element (the byte loads cost more than the rest of
+  // the pass's reads together).
+  const uint8_t* s_used = nullptr;
+  if constexpr (MODE == kPassFirst && IPT % 4 == 0) {
+    uint8_t* stage = reinterpret_cast<uint8_t*>(&s_buf[0][0]) + wave * (kWave * IPT);
+    const int64_t chunk = tile_base + int64_t(wave) * (kWave * IPT);
+    const int64_t mine = chunk + int64_t(lane) * IPT;
+    uint32_t w[IPT / 4];
+    if (mine + IPT <= n) {
+#pragma unroll
+      for (int q = 0; q < IPT / 4; ++q) w[q] = reinterpret_cast<const uint32_t*>(a.used + mine)[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < IPT / 4; ++q) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t p = mine + 4 * q + b;
+          if (p < n) x |= uint32_t(a.used[p]) << (8 * b);
+        }
+        w[q] = x;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < IPT / 4; ++q) reinterpret_cast<uint32_t*>(stage + lane * IPT)[q] = w[q];
+    __syncthreads();
+    s_used = stage;
+  }
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int64_t pos = wave_base + j * kWave;
@@ -247,7 +279,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       if constexpr (MODE == kPassFirst) {
 #pragma unroll
         for (int k = 0; k < K; ++k) v[j][k] = a.src[pos * K + k];
-        v[j][K] = uint32_t(pos) | (a.used[pos] ? 0x80000000u : 0u);
+        const bool used = (IPT % 4 == 0) ? s_used[j * kWave + lane] != 0 : a.used[pos] != 0;
+        v[j][K] = uint32_t(pos) | (used ? 0x80000000u : 0u);
       } else {
         load_words<S>(a.src + pos * S, v[j]);
       }
