@@ -398,6 +398,25 @@ def cpu_baseline(meshgen):
                       f"({sample.num_vtx} vertices, 5% unused)"}
 
 
+def cpu_parallel_baseline(meshgen):
+    """The paper's data-parallel steps on host threads (oracle/parallel_cpu.cpp,
+    a stronger CPU baseline than the serial oracle), on the full timed
+    workload; checked against the closed-form output count."""
+    import oracle
+    oracle.build(force=False)
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
+    m = meshgen.cfg2()
+    oracle.reindex_parallel(m.vtx[:100_000], np.minimum(m.idx[:30_000], 99_999), threads)  # warm-up
+    t0 = time.perf_counter()
+    res = oracle.reindex_parallel(m.vtx, m.idx, threads)
+    dt = time.perf_counter() - t0
+    assert res[0].shape[0] == 2048 * 2048
+    return {"value": m.vtx.shape[0] / dt, "unit": "vertices/s", "threads": threads,
+            "kind": "parallel CPU (the paper's data-parallel steps on host threads)",
+            "seconds": round(dt, 2), "host_cpu": cpu_model(), "sample": "the full timed workload (soup2048)"}
+
+
 def kernels_only(args, torch, mrx, meshgen):
     """Profiler target: W + K re-index steps of the timed workload, then a
     plain device copy of 1 GiB (torch copy_) three times, whose counter
@@ -464,6 +483,8 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(meshgen)
         log("cpu baseline", cpu)
+        extras["cpu_parallel_baseline"] = cpu_parallel_baseline(meshgen)
+        log("cpu parallel baseline", extras["cpu_parallel_baseline"])
 
     n = single["n"]
     ms = single["ms"]

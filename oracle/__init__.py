@@ -19,6 +19,9 @@ library and its Python binding) never imports, links or calls it.
 * ``paper_steps``        — a re-enactment of Section 2 Steps 1-4 in the
                            paper's order and notation (pins the oracle).
 * ``bruteforce``         — O(n^2) grouping by record bytes (pins the oracle).
+* ``reindex_parallel``   — the paper's data-parallel steps on host threads
+                           (parallel_cpu.cpp): a CPU baseline for timing, not
+                           the oracle; tests check it against ``reindex``.
 """
 from __future__ import annotations
 
@@ -30,6 +33,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
+_SRC_PAR = os.path.join(_HERE, "parallel_cpu.cpp")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -39,11 +43,11 @@ INDEX_OUT_OF_RANGE = 3
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.cpp with g++ into oracle/liboracle.so."""
+    """Compile oracle.cpp and parallel_cpu.cpp with g++ into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread",
+                               "-o", tmp, _SRC, _SRC_PAR])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -54,6 +58,11 @@ def _load():
         if not os.path.exists(_LIB_PATH):
             build()
         lib = ctypes.CDLL(_LIB_PATH)
+        lib.cpu_parallel_reindex.restype = ctypes.c_int
+        lib.cpu_parallel_reindex.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_reindex.restype = ctypes.c_int
         lib.oracle_reindex.argtypes = [
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -99,6 +108,32 @@ def reindex(vtx: np.ndarray, idx: np.ndarray):
         raise OracleIndexError(bad.value)
     if rc != OK:
         raise ValueError(f"oracle_reindex: invalid argument (status {rc})")
+    uu = u.value
+    return out_vtx[:uu].copy(), out_idx, old2new, new2old[:uu].copy()
+
+
+def reindex_parallel(vtx: np.ndarray, idx: np.ndarray, threads: int = 8):
+    """Same contract as ``reindex``, computed by the multi-threaded CPU
+    baseline (parallel_cpu.cpp) with ``threads`` host threads."""
+    vtx = np.ascontiguousarray(vtx)
+    assert vtx.ndim == 2 and vtx.dtype.itemsize == 4
+    words = int(vtx.shape[1])
+    v = vtx.view(np.uint32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n = int(v.shape[0])
+    out_vtx = np.empty((max(n, 1), words), dtype=np.uint32)
+    out_idx = np.empty(idx.shape, dtype=np.int32)
+    old2new = np.empty(n, dtype=np.int32)
+    new2old = np.empty(max(n, 1), dtype=np.int32)
+    u = ctypes.c_int64(0)
+    bad = ctypes.c_int64(-1)
+    rc = _load().cpu_parallel_reindex(_ptr(v), n, words, _ptr(idx), int(idx.size), int(threads),
+                                      _ptr(out_vtx), _ptr(out_idx), _ptr(old2new), _ptr(new2old),
+                                      ctypes.byref(u), ctypes.byref(bad))
+    if rc == INDEX_OUT_OF_RANGE:
+        raise OracleIndexError(bad.value)
+    if rc != OK:
+        raise ValueError(f"cpu_parallel_reindex: invalid argument (status {rc})")
     uu = u.value
     return out_vtx[:uu].copy(), out_idx, old2new, new2old[:uu].copy()
 

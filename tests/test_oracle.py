@@ -421,6 +421,25 @@ def test_extract_even_quad_rows_closed_form(n):
     assert int((o2n >= 0).sum()) == 4 * n * n - 2 * n
 
 
+# ----------------------------------------------------------------- parallel CPU baseline
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_parallel_cpu_baseline_matches_oracle(threads):
+    cases = list(_fuzz_cases(60))
+    cases.append((meshgen.cfg1().vtx, meshgen.cfg1().idx))
+    cases.append((meshgen.tet_mesh(8, 0.03, 5).vtx, meshgen.tet_mesh(8, 0.03, 5).idx))
+    cases.append((np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32)))
+    for vtx, idx in cases:
+        exp = oracle.reindex(vtx, idx)
+        got = oracle.reindex_parallel(vtx, idx, threads)
+        for x, y in zip(got, exp):
+            assert np.array_equal(x, y)
+    vtx = np.zeros((10, 2), np.float32)
+    with pytest.raises(oracle.OracleIndexError) as e:
+        oracle.reindex_parallel(vtx, np.array([[1, 2], [3, 10], [-1, 0]], np.int32), threads)
+    assert e.value.pos == 3
+
+
 def test_oracle_mutants_are_caught(tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
