@@ -58,11 +58,12 @@ def _load():
         if not os.path.exists(_LIB_PATH):
             build()
         lib = ctypes.CDLL(_LIB_PATH)
-        lib.cpu_parallel_reindex.restype = ctypes.c_int
-        lib.cpu_parallel_reindex.argtypes = [
-            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        if hasattr(lib, "cpu_parallel_reindex"):  # absent from single-file test builds
+            lib.cpu_parallel_reindex.restype = ctypes.c_int
+            lib.cpu_parallel_reindex.argtypes = [
+                ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_reindex.restype = ctypes.c_int
         lib.oracle_reindex.argtypes = [
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
