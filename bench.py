@@ -454,8 +454,8 @@ def main():
                     help="kernels: only the timed re-index steps and a 1 GiB copy probe (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X "
+              "(multi-GPU sharding is described in the design notes, not implemented).", file=sys.stderr)
         sys.exit(2)
     args.tuning = tuple(int(x) for x in args.tuning.split(",")) if args.tuning else None
 

@@ -7,7 +7,7 @@ checks its outputs bit for bit against variant 0's (a variant that differs is
 a bug and raises), times a few launches with HIP events, and keeps the
 fastest. Results are cached in a JSON file keyed by GPU architecture, record
 width, size bucket and batched/single; a cache with another schema or ABI
-version, or one naming a variant this build does not have, is ignored and
+version, or one naming a variant the loaded library does not have, is ignored and
 re-tuned.
 
 Cache path: $MRX_TUNE_CACHE, else ~/.cache/meshrx/tune.json.
@@ -70,7 +70,7 @@ def save_cache(entries: dict, path: str | None = None):
 
 
 def cached_tuning(entries: dict, key: str, vtx_bytes: int):
-    """The cached variant for `key` if this build still has it, else None."""
+    """The cached variant for `key` if the loaded library still has it, else None."""
     e = entries.get(key)
     if not isinstance(e, dict) or not isinstance(e.get("tuning"), list) or len(e["tuning"]) != 3:
         return None

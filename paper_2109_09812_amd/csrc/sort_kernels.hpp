@@ -116,8 +116,8 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t* __restrict_
 #pragma unroll
   for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
 
-  // Grid-stride over chunks of BLOCK * GROUPS groups: few blocks, so few
-  // global atomics on the (shared, contended) histogram words.
+  // Chunks of BLOCK * GROUPS groups, grid-stride (the launch gives every
+  // chunk its own workgroup: fewer, longer-lived workgroups measured slower).
   const bool vec = (reinterpret_cast<uintptr_t>(vtx) & 15) == 0;
   const int64_t groups = (n + R - 1) / R;
   for (int64_t g0 = int64_t(blockIdx.x) * (BLOCK * GROUPS); g0 < groups;
@@ -421,15 +421,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // ---- scatter: consecutive q of one digit go to consecutive addresses
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
-    if (int64_t(opos[r]) < n) {
-#ifdef MRX_SCATTER_NT
-      uint32_t* d = a.dst + int64_t(opos[r]) * S;
-#pragma unroll
-      for (int w = 0; w < S; ++w) __builtin_nontemporal_store(v[r][w], d + w);
-#else
-      store_words<S>(a.dst + int64_t(opos[r]) * S, v[r]);
-#endif
-    }
+    if (int64_t(opos[r]) < n) store_words<S>(a.dst + int64_t(opos[r]) * S, v[r]);
   }
 }
 

@@ -234,7 +234,7 @@ def test_autotune_cache_validation(tmp_path, monkeypatch):
     loaded = at.load_cache(path)
     assert loaded == json.loads(json.dumps(entries))
     assert at.cached_tuning(loaded, "a", 12).as_tuple() == t0
-    assert at.cached_tuning(loaded, "b", 12) is None       # variant not in this build
+    assert at.cached_tuning(loaded, "b", 12) is None       # variant not in the library
     assert at.cached_tuning(loaded, "c", 12) is None       # malformed
     assert at.cached_tuning(loaded, "missing", 12) is None
     k = at.shape_key("gfx950", 12, 26_398_316, False)
