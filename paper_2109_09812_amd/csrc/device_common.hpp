@@ -266,11 +266,21 @@ __device__ __forceinline__ void store_words(uint32_t* __restrict__ p, const uint
   }
 }
 
-// Mesh id of global vertex id `id` in a packed batch: the b with
-// off[b] <= id < off[b+1] (binary search; off has nmesh+1 entries).
+// Mesh of a packed id: the b with off[b] <= id < off[b+1] (binary search;
+// off has nmesh+1 entries). With `tab` (tab[q] = mesh of id q << kMeshTabShift,
+// clamped to the last id; see k_mesh_table) the search only spans the meshes
+// that start inside id's bucket of 2^kMeshTabShift ids, a step or two
+// instead of log2(nmesh) dependent loads.
+constexpr int kMeshTabShift = 8;
+
 __device__ __forceinline__ uint32_t mesh_of(const int64_t* __restrict__ off, int32_t nmesh,
-                                            int64_t id) {
+                                            int64_t id, const int32_t* __restrict__ tab = nullptr) {
   int32_t lo = 0, hi = nmesh;  // invariant: off[lo] <= id < off[hi]
+  if (tab) {
+    const int64_t q = id >> kMeshTabShift;
+    lo = max(0, min(tab[q], nmesh - 1));
+    hi = min(nmesh, max(tab[q + 1] + 1, lo + 1));
+  }
   while (hi - lo > 1) {
     int32_t mid = (lo + hi) >> 1;
     if (off[mid] <= id) lo = mid; else hi = mid;

@@ -51,13 +51,24 @@ __global__ void k_batch_offsets(const int64_t* __restrict__ vtx_off, int32_t nme
 }
 
 __global__ void k_localize_new2old(int32_t* __restrict__ new2old, const int64_t* __restrict__ total_used,
-                                   const int64_t* __restrict__ vtx_off, int32_t nmesh) {
+                                   const int64_t* __restrict__ vtx_off, int32_t nmesh,
+                                   const int32_t* __restrict__ vtx_tab) {
   const int64_t u = *total_used;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < u; j += stride) {
     const int32_t g = new2old[j];
-    new2old[j] = g - int32_t(vtx_off[mesh_of(vtx_off, nmesh, g)]);
+    new2old[j] = g - int32_t(vtx_off[mesh_of(vtx_off, nmesh, g, vtx_tab)]);
   }
+}
+
+// tab[q] = mesh of packed id min(q << kMeshTabShift, total - 1), q in [0, nq),
+// the bucket table that lets mesh_of search a handful of meshes.
+__global__ void k_mesh_table(const int64_t* __restrict__ off, int32_t nmesh, int64_t total, int32_t* tab,
+                             int64_t nq) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t x = min(q << kMeshTabShift, total - 1);
+  tab[q] = int32_t(mesh_of(off, nmesh, x));
 }
 
 namespace {
@@ -155,7 +166,8 @@ struct Layout {
          used_g = 0, zero_end = 0;
   int64_t tiles_elem = 0;
   // scratch
-  size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, total = 0;
+  size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, total = 0;
+  int64_t vtx_tab_n = 0, elem_tab_n = 0;
 };
 
 // Element tiles of the sub-mesh selection (k_select_elements).
@@ -192,6 +204,12 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
   L.rep = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
   L.cmap = off;     off = align_up(off + sizeof(int32_t) * size_t(n));
+  if (nmesh > 1) {  // bucket tables of the vertex and element offsets (mesh_of)
+    L.vtx_tab_n = (std::max<int64_t>(n, 1) - 1) / (int64_t(1) << kMeshTabShift) + 2;
+    L.elem_tab_n = (std::max<int64_t>(num_idx, 1) - 1) / (int64_t(1) << kMeshTabShift) + 2;
+    L.vtx_tab = off;  off = align_up(off + sizeof(int32_t) * size_t(L.vtx_tab_n));
+    L.elem_tab = off; off = align_up(off + sizeof(int32_t) * size_t(L.elem_tab_n));
+  }
   L.total = off;
   return L;
 }
@@ -349,7 +367,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
   if (m > 0) {
     prof_mark("mark_used", s);
     hipLaunchKernelGGL((k_mark_used<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       nullptr, nullptr, 0, live_elems, used_v, status);
+                       nullptr, nullptr, 0, nullptr, live_elems, used_v, status);
   }
   if (n > 0) {
     // Step 2: stable LSD radix sort of (record, id | used << 31)
@@ -413,13 +431,13 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       f.pairs, cmap, n, nullptr, nullptr, 0, old2new);
+                       f.pairs, cmap, n, nullptr, nullptr, 0, nullptr, old2new);
   }
   // Step 4: remap the index array
   if (m > 0) {
     prof_mark("remap", s);
     hipLaunchKernelGGL((k_remap<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       nullptr, nullptr, 0, live_elems, old2new, out_idx);
+                       nullptr, nullptr, 0, nullptr, live_elems, old2new, out_idx);
   }
   prof_mark(nullptr, s);
   return check_launch();
@@ -579,16 +597,33 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
   int32_t* status = dev_status ? dev_status : &ctl->status;
   const int P = L.P_key + L.P_mesh;
+  int32_t* vtab = L.vtx_tab_n ? reinterpret_cast<int32_t*>(ws + L.vtx_tab) : nullptr;
+  int32_t* etab = L.elem_tab_n ? reinterpret_cast<int32_t*>(ws + L.elem_tab) : nullptr;
 
   prof_mark("fill_zero", s);
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status,
                      static_cast<int64_t*>(nullptr), static_cast<int64_t*>(nullptr));
+  const int64_t num_e = total_elems;
+  if (vtab && n > 0) {
+    prof_mark("mesh_tables", s);
+    hipLaunchKernelGGL(k_mesh_table, dim3((L.vtx_tab_n + 255) / 256), dim3(256), 0, s, vtx_offsets, num_meshes,
+                       n, vtab, L.vtx_tab_n);
+  } else {
+    vtab = nullptr;
+  }
+  if (etab && num_e > 0) {
+    const int64_t nq = (num_e - 1) / (int64_t(1) << kMeshTabShift) + 2;  // <= L.elem_tab_n
+    hipLaunchKernelGGL(k_mesh_table, dim3((nq + 255) / 256), dim3(256), 0, s, elem_offsets, num_meshes, num_e,
+                       etab, nq);
+  } else {
+    etab = nullptr;
+  }
   if (m > 0) {
     prof_mark("mark_used", s);
     hipLaunchKernelGGL((k_mark_used<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int64_t*>(nullptr), used_v,
-                       status);
+                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int32_t*>(etab),
+                       static_cast<const int64_t*>(nullptr), used_v, status);
   }
   if (n > 0) {
     prof_mark("histogram", s);
@@ -612,6 +647,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
       a.status = status;
       a.n = n;
       a.mesh_off = vtx_offsets;
+      a.mesh_tab = vtab;
       a.nmesh = num_meshes;
       a.tag = uint32_t(p + 1);
       int mode = kPassKey;
@@ -639,6 +675,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     f.ctl = ctl;
     f.status = status;
     f.mesh_off = vtx_offsets;
+    f.mesh_tab = vtab;
     f.nmesh = num_meshes;
     f.tag = uint32_t(P + 1);
     prof_mark("flag_scan", s);
@@ -667,11 +704,12 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
                        out_vtx_offsets);
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<true>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       f.pairs, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes, old2new);
+                       f.pairs, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes,
+                       static_cast<const int32_t*>(vtab), old2new);
     if (new2old) {
       prof_mark("localize_new2old", s);
       hipLaunchKernelGGL(k_localize_new2old, dim3(grid_for(n, 256)), dim3(256), 0, s, new2old,
-                         &ctl->num_used, vtx_offsets, num_meshes);
+                         &ctl->num_used, vtx_offsets, num_meshes, static_cast<const int32_t*>(vtab));
     }
   } else {
     prof_mark("batch_offsets", s);
@@ -683,8 +721,8 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   if (m > 0) {
     prof_mark("remap", s);
     hipLaunchKernelGGL((k_remap<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int64_t*>(nullptr), old2new,
-                       out_idx);
+                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int32_t*>(etab),
+                       static_cast<const int64_t*>(nullptr), old2new, out_idx);
   }
   prof_mark(nullptr, s);
   return check_launch();

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kRandBlock) void k_mark_used(const int32_t* __restr
                                                           int32_t arity, int64_t n,
                                                           const int64_t* __restrict__ vtx_off,
                                                           const int64_t* __restrict__ elem_off,
-                                                          int32_t nmesh,
+                                                          int32_t nmesh, const int32_t* __restrict__ elem_tab,
                                                           const int64_t* __restrict__ live_elems,
                                                           uint8_t* __restrict__ used, int32_t* status) {
   // live_elems (device, nullable): only the first *live_elems elements count
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kRandBlock) void k_mark_used(const int32_t* __restr
     if (k >= m) break;
     int64_t lo = 0, cnt = n;
     if constexpr (BATCHED) {
-      const uint32_t b = mesh_of(elem_off, nmesh, k / arity);
+      const uint32_t b = mesh_of(elem_off, nmesh, k / arity, elem_tab);
       lo = vtx_off[b];
       cnt = vtx_off[b + 1] - lo;
     }
@@ -74,6 +74,7 @@ struct FlagScanArgs {
   Control* ctl;
   int32_t* status;
   const int64_t* mesh_off; // batched: [nmesh+1]; head also at every mesh start
+  const int32_t* mesh_tab; // batched: bucket table of mesh_off (mesh_of)
   int32_t nmesh;
   uint32_t tag;
 };
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
     if (valid) {
       h = (pos == 0) || differs;
       if constexpr (BATCHED) {
-        const uint32_t b = mesh_of(a.mesh_off, a.nmesh, pos);
+        const uint32_t b = mesh_of(a.mesh_off, a.nmesh, pos, a.mesh_tab);
         h = h || (a.mesh_off[b] == pos);
       }
     }
@@ -286,7 +287,8 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
                                                                 const int32_t* __restrict__ cmap, int64_t n,
                                                                 const int64_t* __restrict__ vtx_off,
                                                                 const int64_t* __restrict__ out_off,
-                                                                int32_t nmesh, int32_t* __restrict__ old2new) {
+                                                                int32_t nmesh, const int32_t* __restrict__ vtx_tab,
+                                                                int32_t* __restrict__ old2new) {
   const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kScatterItems) + threadIdx.x;
   uint2 p[kScatterItems];
   int32_t c[kScatterItems];
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
     if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) continue;  // past the end (or a failed wait)
     int32_t cc = c[it] < 0 ? -1 : c[it];
     if constexpr (BATCHED) {
-      if (cc >= 0) cc -= int32_t(out_off[mesh_of(vtx_off, nmesh, int64_t(p[it].y))]);
+      if (cc >= 0) cc -= int32_t(out_off[mesh_of(vtx_off, nmesh, int64_t(p[it].y), vtx_tab)]);
     }
     old2new[p[it].y] = cc;
   }
@@ -318,6 +320,7 @@ template <bool BATCHED>
 __global__ __launch_bounds__(kRandBlock) void k_remap(const int32_t* idx, int64_t m, int32_t arity, int64_t n,
                                                       const int64_t* __restrict__ vtx_off,
                                                       const int64_t* __restrict__ elem_off, int32_t nmesh,
+                                                      const int32_t* __restrict__ elem_tab,
                                                       const int64_t* __restrict__ live_elems,
                                                       const int32_t* __restrict__ old2new, int32_t* out_idx) {
   if (live_elems) m = min(m, *live_elems * arity);  // see k_mark_used
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(kRandBlock) void k_remap(const int32_t* idx, int64_
       const int32_t v = stream_load(idx + k);
       int64_t lo = 0, cnt = n;
       if constexpr (BATCHED) {
-        const uint32_t b = mesh_of(elem_off, nmesh, k / arity);
+        const uint32_t b = mesh_of(elem_off, nmesh, k / arity, elem_tab);
         lo = vtx_off[b];
         cnt = vtx_off[b + 1] - lo;
       }

@@ -30,6 +30,7 @@ struct SortPassArgs {
   Control* ctl;
   int32_t* status;
   const int64_t* mesh_off;      // mesh passes: [nmesh+1] vertex offsets
+  const int32_t* mesh_tab;      // mesh passes: bucket table of mesh_off (mesh_of)
   int32_t nmesh;
   // The digit is bits [shift, shift + D) of (word_hi:word_lo). The words are
   // selected with per-word masks (all-ones for the chosen word, zero for the
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   for (int j = 0; j < IPT; ++j) {
     if constexpr (MODE == kPassMesh) {
       const int64_t pos = wave_base + j * kWave;
-      const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu)) : 0u;
+      const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
       dig[j] = (m >> a.shift) & MASK;
     } else {
       dig[j] = masked_digit<D, K>(v[j], a.lo_mask, a.hi_mask, a.shift);
