@@ -17,11 +17,11 @@ namespace mrx {
 __global__ __launch_bounds__(256) void k_offset_indices(const int32_t* idx, int64_t m, int32_t arity,
                                                         const int64_t* __restrict__ vtx_off,
                                                         const int64_t* __restrict__ elem_off, int32_t nmesh,
-                                                        int32_t* out) {
+                                                        const int32_t* __restrict__ elem_tab, int32_t* out) {
   const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (k >= m) return;
   const int32_t v = idx[k];
-  const uint32_t b = mesh_of(elem_off, nmesh, k / arity);
+  const uint32_t b = mesh_of(elem_off, nmesh, k / arity, elem_tab);
   const int64_t lo = vtx_off[b], cnt = vtx_off[b + 1] - lo;
   out[k] = (v >= 0 && int64_t(v) < cnt && lo >= 0) ? int32_t(lo + v) : -1;
 }

@@ -204,11 +204,13 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
   L.rep = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
   L.cmap = off;     off = align_up(off + sizeof(int32_t) * size_t(n));
-  if (nmesh > 1) {  // bucket tables of the vertex and element offsets (mesh_of)
+  // bucket tables of the element offsets (batch, merge) and vertex offsets
+  // (batch) for mesh_of; the element table is small enough to always reserve
+  L.elem_tab_n = (std::max<int64_t>(num_idx, 1) - 1) / (int64_t(1) << kMeshTabShift) + 2;
+  L.elem_tab = off; off = align_up(off + sizeof(int32_t) * size_t(L.elem_tab_n));
+  if (nmesh > 1) {
     L.vtx_tab_n = (std::max<int64_t>(n, 1) - 1) / (int64_t(1) << kMeshTabShift) + 2;
-    L.elem_tab_n = (std::max<int64_t>(num_idx, 1) - 1) / (int64_t(1) << kMeshTabShift) + 2;
     L.vtx_tab = off;  off = align_up(off + sizeof(int32_t) * size_t(L.vtx_tab_n));
-    L.elem_tab = off; off = align_up(off + sizeof(int32_t) * size_t(L.elem_tab_n));
   }
   L.total = off;
   return L;
@@ -749,9 +751,14 @@ mrx_status mrx_merge_meshes(const void* vtx, const int64_t* vtx_offsets, int64_t
   const int64_t m = total_elems * arity;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (m > 0) {
+    int32_t* etab = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + L.elem_tab);
+    const int64_t nq = (total_elems - 1) / (int64_t(1) << kMeshTabShift) + 2;  // <= L.elem_tab_n
+    prof_mark("mesh_tables", s);
+    hipLaunchKernelGGL(k_mesh_table, dim3((nq + 255) / 256), dim3(256), 0, s, elem_offsets, num_meshes,
+                       total_elems, etab, nq);
     prof_mark("offset_indices", s);
     hipLaunchKernelGGL(k_offset_indices, dim3((m + 255) / 256), dim3(256), 0, s, idx, m, arity, vtx_offsets,
-                       elem_offsets, num_meshes, out_idx);
+                       elem_offsets, num_meshes, static_cast<const int32_t*>(etab), out_idx);
   }
   return launch_single(*v, L, vtx, total_vtx, vtx_bytes, out_idx, total_elems, arity, nullptr, out_vtx,
                        out_idx, old2new, new2old, out_num_vtx, dev_status, workspace, tuning, stream);
