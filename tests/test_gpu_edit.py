@@ -198,3 +198,65 @@ def test_preallocated_merger_and_extractor_relaunch():
         r = x.result()
         assert r.num_elems_out == int(k.sum())
         _same(_host(r), oracle.extract(m.vtx, m.idx, k), f"extractor{rep}")
+
+
+def _capture(launch):
+    """Capture one launch into a graph (after an eager warm-up on a side stream)."""
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=DEV)
+    side.wait_stream(torch.cuda.current_stream(DEV))
+    with torch.cuda.stream(side):
+        launch()
+    torch.cuda.current_stream(DEV).wait_stream(side)
+    with torch.cuda.graph(g):
+        launch()
+    return g
+
+
+def test_graph_replays_single_merge_extract():
+    """Reindexer, MeshMerger and SubmeshExtractor captured once and replayed
+    on refilled inputs, with eager work between replays; every replay must
+    match the oracle."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(123)
+    # single mesh: same shape, new vertex order each replay
+    m = meshgen.grid_soup(120, 0.05, 77, "graph")
+    v = torch.from_numpy(np.ascontiguousarray(m.vtx).view(np.int32)).to(DEV)
+    i = torch.from_numpy(m.idx).to(DEV)
+    rx = mrx.Reindexer(v, i)
+    g = _capture(rx.launch)
+    for rep in range(3):
+        p = rng.permutation(m.vtx.shape[0])
+        inv = np.empty_like(p)
+        inv[p] = np.arange(p.size)
+        vtx_r, idx_r = m.vtx[p], inv[m.idx].astype(np.int32)
+        v.copy_(torch.from_numpy(np.ascontiguousarray(vtx_r).view(np.int32)))
+        i.copy_(torch.from_numpy(idx_r))
+        _say("graph single replay", rep)
+        g.replay()
+        _same(_host(rx.result()), oracle.reindex(vtx_r, idx_r), f"graph single {rep}")
+        _ = (v.float() * 2).sum().item()
+    # merge
+    b = meshgen.batched(20, 100, 2000, 0.05, 78)
+    tensors = _dev_batch(b)
+    mg = mrx.MeshMerger(*tensors)
+    g = _capture(mg.launch)
+    exp = oracle.merge(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
+    for rep in range(2):
+        _say("graph merge replay", rep)
+        g.replay()
+        _same(_host(mg.result()), exp, f"graph merge {rep}")
+        _ = (tensors[0].float() * 2).sum().item()
+    # extract: new keep flags each replay
+    keep = torch.zeros(m.idx.shape[0], dtype=torch.bool, device=DEV)
+    x = mrx.SubmeshExtractor(v, i, keep)
+    g = _capture(x.launch)
+    for rep, frac in enumerate((0.5, 0.1, 0.9)):
+        k = rng.random(m.idx.shape[0]) < frac
+        keep.copy_(torch.from_numpy(k))
+        _say("graph extract replay", rep)
+        g.replay()
+        r = x.result()
+        assert r.num_elems_out == int(k.sum())
+        _same(_host(r), oracle.extract(vtx_r, idx_r, k), f"graph extract {rep}")
+        _ = (v.float() * 2).sum().item()
