@@ -150,3 +150,33 @@ def test_batched_all_tunings_and_autotune(tmp_path):
     t, report = autotune.autotune(tensors[0], tensors[2], tensors[1], tensors[3], reps=2,
                                   path=str(tmp_path / "t.json"))
     check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=t))
+
+
+def test_cfg4_full_batch_sampled():
+    """The full 4096-mesh batch (~328M vertices) in one launch sequence:
+    every mesh's output count matches its closed form, and sampled meshes
+    match the per-mesh oracle bit for bit."""
+    import paper_2109_09812_amd as mrx
+    _say("batch4096: generate")
+    b = meshgen.cfg4()
+    _say("batch4096: re-index", b.vtx.shape[0], "vertices")
+    res = mrx.reindex_mesh_batched(*to_dev(b))
+    offs = res.out_vtx_offsets.cpu().numpy()
+    assert np.array_equal(np.diff(offs), b.expected_unique)
+    rng = np.random.default_rng(4096)
+    sizes = np.diff(b.vtx_offsets)
+    small = np.flatnonzero(sizes < 150_000)
+    pick = np.concatenate([rng.choice(small, 10, replace=False), [int(np.argmax(sizes)), 0, b.num_meshes - 1]])
+    ov_all = res.out_vtx.cpu().numpy().view(np.uint32)
+    oi_all = res.out_idx.cpu().numpy()
+    o2n_all = res.old2new.cpu().numpy()
+    n2o_all = res.new2old.cpu().numpy()
+    for mi in pick:
+        v0, v1 = int(b.vtx_offsets[mi]), int(b.vtx_offsets[mi + 1])
+        e0, e1 = int(b.elem_offsets[mi]), int(b.elem_offsets[mi + 1])
+        _say("batch4096: oracle mesh", int(mi), v1 - v0, "vertices")
+        ov, oi, o2n, n2o = oracle.reindex(b.vtx[v0:v1], b.idx[e0:e1])
+        assert np.array_equal(ov_all[offs[mi]:offs[mi + 1]], ov)
+        assert np.array_equal(oi_all[e0:e1], oi)
+        assert np.array_equal(o2n_all[v0:v1], o2n)
+        assert np.array_equal(n2o_all[offs[mi]:offs[mi + 1]], n2o)
