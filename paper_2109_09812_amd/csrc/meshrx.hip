@@ -283,14 +283,6 @@ mrx_status validate_common(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   return MRX_OK;
 }
 
-}  // namespace
-}  // namespace mrx
-
-using namespace mrx;
-
-namespace mrx {
-namespace {
-
 // Checks shared by every single-mesh call; on success *layout describes the
 // workspace. `extra` lists caller buffers of the call that must not overlap
 // any of the others (NULL entries are ignored).
@@ -448,6 +440,8 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
 }  // namespace
 }  // namespace mrx
 
+using namespace mrx;
+
 extern "C" {
 
 int32_t mrx_abi_version(void) { return MRX_ABI_VERSION; }
@@ -577,7 +571,8 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
                  {vtx_offsets, ob}, {elem_offsets, ob}, {idx == out_idx ? nullptr : idx, ib}}) ||
       !disjoint({{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
                  {out_vtx_offsets, ob}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
-                 {vtx_offsets, ob}, {elem_offsets, ob}}))
+                 {vtx_offsets, ob}, {elem_offsets, ob}}) ||
+      (idx != out_idx && overlaps(idx, ib, out_idx, ib)))  // in place, or not at all
     return MRX_ERR_INVALID_ARGUMENT;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_);

@@ -158,6 +158,8 @@ def test_batched_rejects_bad_arguments():
     assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # misaligned offsets
     bad = list(base); bad[16] = 256
     assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
+    bad = list(base); bad[11] = B + 4
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # out_idx overlaps idx
 
 
 def test_merge_rejects_bad_arguments():
