@@ -94,6 +94,59 @@ def kernel_table(records):
     return {k: (c, t / c) for k, (c, t) in agg.items()}
 
 
+def step_distribution(fn, steps, torch):
+    """Per-step times (one event pair around each step): median, p10, p90."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return {"median_ms": round(float(np.median(t)), 5), "p10_ms": round(float(np.percentile(t, 10)), 5),
+            "p90_ms": round(float(np.percentile(t, 90)), 5)}
+
+
+def transfer_times(mesh, rx, torch):
+    """Host<->device copies around one re-index (pinned host buffers), timed
+    apart from the GPU-resident step: inputs up, all four outputs down."""
+    dev = rx.vtx.device
+    hv = torch.from_numpy(mesh.vtx.view("int32")).pin_memory()
+    hi = torch.from_numpy(mesh.idx).pin_memory()
+    outs = [rx.out_vtx, rx.out_idx, rx.old2new, rx.new2old]
+    houts = [torch.empty(o.shape, dtype=o.dtype, pin_memory=True) for o in outs]
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    a.record()
+    rx.vtx.copy_(hv, non_blocking=True)
+    rx.idx.copy_(hi, non_blocking=True)
+    b.record()
+    for h, o in zip(houts, outs):
+        h.copy_(o, non_blocking=True)
+    c.record()
+    torch.cuda.synchronize()
+    up, down = a.elapsed_time(b), b.elapsed_time(c)
+    up_b = hv.numel() * 4 + hi.numel() * 4
+    down_b = sum(o.numel() * o.element_size() for o in outs)
+    return {"h2d_ms": round(up, 3), "h2d_GBps": round(up_b / (up * 1e-3) / 1e9, 1),
+            "d2h_ms": round(down, 3), "d2h_GBps": round(down_b / (down * 1e-3) / 1e9, 1)}
+
+
+def copy_probe(torch, gib=1):
+    """Attainable device-to-device copy bandwidth (read + write bytes / time)."""
+    dev = torch.device("cuda:0")
+    a = torch.empty(gib << 28, dtype=torch.int32, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    ms, _ = timed_steps(lambda: b.copy_(a), 5, torch)
+    out = round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def choose_tuning(args, vtx, idx):
     """--tuning if given, else the autotuner's pick (cached per workload shape)."""
     tuning = args.tuning
@@ -122,6 +175,8 @@ def bench_single(args, torch, mrx, meshgen):
     torch.cuda.synchronize()
     ms, wall = timed_steps(rx.launch, args.steps, torch)
     log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f}s)")
+    dist = step_distribution(rx.launch, args.steps, torch)
+    xfer = transfer_times(m, rx, torch)
 
     # per-kernel durations from HIP events recorded on the launch stream
     from paper_2109_09812_amd import _lib
@@ -159,7 +214,7 @@ def bench_single(args, torch, mrx, meshgen):
     for name, b in model.items():
         if name in kernels and table[name][1] > 0:
             kernels[name]["model_GBps"] = round(b / (table[name][1] * 1e-3) / 1e9, 1)
-    return dict(n=n, m=e * a, u=u, ms=ms, ms_prof=ms_prof, kernels=kernels, extract=extract,
+    return dict(n=n, m=e * a, u=u, ms=ms, ms_prof=ms_prof, kernels=kernels, extract=extract, dist=dist, xfer=xfer,
                 roofline_pass=dict(achieved=achieved, bytes=pass_bytes, mean_ms=passes[1]),
                 step_model_bytes_sort=step_bytes, r_bytes=r_bytes)
 
@@ -515,6 +570,9 @@ def main():
         "cpu_baseline": cpu,
         "kernels": single["kernels"],
         "ms_per_step_profiled": round(single["ms_prof"], 5),
+        "step_distribution": single["dist"],
+        "transfers_not_in_value": single["xfer"],
+        "device_copy_GBps": copy_probe(torch),
         "extract": single["extract"],
     }
     line.update(extras)
