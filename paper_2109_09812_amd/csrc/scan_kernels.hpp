@@ -289,7 +289,18 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
                                                                 const int64_t* __restrict__ out_off,
                                                                 int32_t nmesh, const int32_t* __restrict__ vtx_tab,
                                                                 int32_t* __restrict__ old2new) {
-  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kScatterItems) + threadIdx.x;
+  constexpr int TILE = kRandBlock * kScatterItems;
+  __shared__ int32_t s_cmap[TILE];
+  __shared__ uint32_t s_g[2];
+  const int64_t t0 = int64_t(blockIdx.x) * TILE;
+  const int64_t base = t0 + threadIdx.x;
+  // A tile's group ids are non-decreasing and grow by at most one per
+  // position, so cmap[g_first .. g_last] (at most TILE entries) is staged in
+  // LDS with coalesced loads instead of one gather per element.
+  if (threadIdx.x == 0) {
+    s_g[0] = pairs[t0].x;
+    s_g[1] = pairs[min(t0 + TILE, n) - 1].x;
+  }
   uint2 p[kScatterItems];
   int32_t c[kScatterItems];
 #pragma unroll
@@ -301,9 +312,18 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __r
       p[it] = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
     }
   }
+  __syncthreads();
+  const uint32_t g0 = s_g[0];
+  const int64_t span = min(int64_t(TILE), int64_t(s_g[1]) - int64_t(g0) + 1);
+  for (int64_t i = threadIdx.x; i < span; i += kRandBlock)
+    s_cmap[i] = (int64_t(g0) + i < n) ? cmap[int64_t(g0) + i] : -1;
+  __syncthreads();
 #pragma unroll
-  for (int it = 0; it < kScatterItems; ++it)
-    c[it] = (int64_t(p[it].x) < n && int64_t(p[it].y) < n) ? cmap[p[it].x] : -1;
+  for (int it = 0; it < kScatterItems; ++it) {
+    const int64_t off = int64_t(p[it].x) - int64_t(g0);
+    if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) c[it] = -1;
+    else c[it] = (off >= 0 && off < span) ? s_cmap[off] : cmap[p[it].x];  // outside: only after a failed wait
+  }
 #pragma unroll
   for (int it = 0; it < kScatterItems; ++it) {
     if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) continue;  // past the end (or a failed wait)
