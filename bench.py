@@ -207,7 +207,9 @@ def bench_single(args, torch, mrx, meshgen):
         "onesweep_first": n * r_bytes + n + n * s_elem,
         "onesweep": pass_bytes,
     }
-    step_bytes = model["histogram"] + model["mark_used"] + model["onesweep_first"] + \
+    # the used marking and the histograms run as one launch where they fit
+    model["mark_histogram"] = model["mark_used"] + model["histogram"]
+    step_bytes = model["mark_histogram"] + model["onesweep_first"] + \
         model["onesweep"] * max(0, passes[0] // max(1, args.steps))
     kernels = {name: {"launches_per_step": c // args.steps, "mean_ms": round(t, 5)}
                for name, (c, t) in table.items()}

@@ -357,16 +357,23 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
                        reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
                        static_cast<int64_t*>(nullptr));
   }
-  // Step 1: mark referenced vertices (and report out-of-range entries)
-  if (m > 0) {
+  // Step 1: mark referenced vertices (and report out-of-range entries),
+  // with the digit histograms of Step 2 in the same launch where it applies
+  const MarkArgs mark{idx, m, arity, n, nullptr, nullptr, 0, nullptr, live_elems, used_v, status};
+  const bool fused = v.mark_hist_applies(n, m);
+  if (fused) {
+    prof_mark("mark_histogram", s);
+    v.mark_hist(mark, false, static_cast<const uint32_t*>(vtx), n, hist, s);
+  } else if (m > 0) {
     prof_mark("mark_used", s);
-    hipLaunchKernelGGL((k_mark_used<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       nullptr, nullptr, 0, nullptr, live_elems, used_v, status);
+    hipLaunchKernelGGL((k_mark_used<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, mark);
   }
   if (n > 0) {
     // Step 2: stable LSD radix sort of (record, id | used << 31)
-    prof_mark("histogram", s);
-    v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    if (!fused) {
+      prof_mark("histogram", s);
+      v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    }
     prof_mark("scan_buckets", s);
     v.scan(hist, L.P_key, s);
     const uint32_t* src = static_cast<const uint32_t*>(vtx);
@@ -616,15 +623,20 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   } else {
     etab = nullptr;
   }
-  if (m > 0) {
+  const MarkArgs mark{idx, m, arity, n, vtx_offsets, elem_offsets, num_meshes, etab, nullptr, used_v, status};
+  const bool fused = v.mark_hist_applies(n, m);
+  if (fused) {
+    prof_mark("mark_histogram", s);
+    v.mark_hist(mark, true, static_cast<const uint32_t*>(vtx), n, hist, s);
+  } else if (m > 0) {
     prof_mark("mark_used", s);
-    hipLaunchKernelGGL((k_mark_used<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
-                       vtx_offsets, elem_offsets, num_meshes, static_cast<const int32_t*>(etab),
-                       static_cast<const int64_t*>(nullptr), used_v, status);
+    hipLaunchKernelGGL((k_mark_used<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, mark);
   }
   if (n > 0) {
-    prof_mark("histogram", s);
-    v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    if (!fused) {
+      prof_mark("histogram", s);
+      v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
+    }
     prof_mark("mesh_histogram", s);
     v.mesh_hist(vtx_offsets, num_meshes, L.P_mesh, hist + size_t(L.P_key) * v.radix(), s);
     prof_mark("scan_buckets", s);

@@ -16,6 +16,33 @@ constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 16;
 constexpr int kScanTile = kScanBlock * kScanIpt;
 
+// Step 1 and the key-pass digit histograms of Step 2 as one launch. The two
+// read different arrays and are held up by different units (scattered byte
+// stores for the marking, LDS atomics for the histograms), so their tiles are
+// spread evenly over one grid and run side by side. With H histogram tiles
+// and M marking tiles, h(b) = floor(b * H / (H + M)) counts the histogram
+// tiles before block b: block b is histogram tile h(b) if h(b + 1) > h(b),
+// else marking tile b - h(b).
+template <int K, int D, int BLOCK, int GROUPS, bool BATCHED>
+__global__ __launch_bounds__(BLOCK) void k_mark_histogram(MarkArgs ma, const uint32_t* __restrict__ vtx,
+                                                          int64_t n, uint32_t* __restrict__ hist,
+                                                          int64_t hist_tiles, int64_t mark_tiles) {
+  static_assert(BLOCK == kRandBlock, "both halves use the marking block shape");
+  constexpr int P = (32 * K + D - 1) / D;
+  __shared__ uint32_t s_h[P << D];
+  const int64_t total = hist_tiles + mark_tiles;
+  const int64_t b = blockIdx.x;
+  const int64_t h0 = b * hist_tiles / total;
+  const int64_t h1 = (b + 1) * hist_tiles / total;
+  if (h1 > h0) {
+    for (int i = threadIdx.x; i < (P << D); i += BLOCK) s_h[i] = 0;
+    __syncthreads();
+    histogram_chunk<K, D, BLOCK, GROUPS>(vtx, n, hist, s_h, h0);
+  } else {
+    mark_used_tile<BATCHED>(ma, b - h0);
+  }
+}
+
 struct SortVariant {
   int K = 0, D = 0, block = 0, ipt = 0;
   // one LSD pass over `grid` tiles; `wide` selects 64-bit tagged look-back
@@ -23,6 +50,12 @@ struct SortVariant {
   void (*pass)(const SortPassArgs&, int mode, bool wide, int64_t grid, hipStream_t) = nullptr;
   // digit histograms of all key passes
   void (*hist)(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t) = nullptr;
+  // Step 1 fused with `hist` (k_mark_histogram), where mark_hist_applies:
+  // there is something to mark and to sort, and the histograms are small
+  // enough to share the CU with the marking waves
+  bool (*mark_hist_applies)(int64_t n, int64_t m) = nullptr;
+  void (*mark_hist)(const MarkArgs& mark, bool batched, const uint32_t* vtx, int64_t n, uint32_t* hist,
+                    hipStream_t) = nullptr;
   // digit histograms of the mesh-id passes of a batch
   void (*mesh_hist)(const int64_t* off, int32_t nmesh, int32_t passes, uint32_t* hist,
                     hipStream_t) = nullptr;

@@ -20,39 +20,52 @@ constexpr int kScatterItems = 16;    // k_scatter_old2new
 
 // Step 1: used[v] = 1 for every referenced vertex v. Batched meshes carry
 // mesh-local indices; the element's mesh supplies the vertex offset.
+struct MarkArgs {
+  const int32_t* idx;          // [m] index entries
+  int64_t m;                   // capacity in entries (num_elems * arity)
+  int32_t arity;
+  int64_t n;                   // vertices
+  const int64_t* vtx_off;      // batched: [nmesh+1] vertex offsets
+  const int64_t* elem_off;     // batched: [nmesh+1] element offsets
+  int32_t nmesh;
+  const int32_t* elem_tab;     // batched: bucket table of elem_off (mesh_of)
+  const int64_t* live_elems;   // device, nullable: only the first *live_elems elements count
+  uint8_t* used;               // [n], zeroed
+  int32_t* status;
+};
+
+// One tile of kRandBlock * kRandItems entries (tile = the workgroup's share).
 template <bool BATCHED>
-__global__ __launch_bounds__(kRandBlock) void k_mark_used(const int32_t* __restrict__ idx, int64_t m,
-                                                          int32_t arity, int64_t n,
-                                                          const int64_t* __restrict__ vtx_off,
-                                                          const int64_t* __restrict__ elem_off,
-                                                          int32_t nmesh, const int32_t* __restrict__ elem_tab,
-                                                          const int64_t* __restrict__ live_elems,
-                                                          uint8_t* __restrict__ used, int32_t* status) {
-  // live_elems (device, nullable): only the first *live_elems elements count
-  if (live_elems) m = min(m, *live_elems * arity);
-  const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
+__device__ __forceinline__ void mark_used_tile(const MarkArgs& a, int64_t tile) {
+  const int64_t m = a.live_elems ? min(a.m, *a.live_elems * a.arity) : a.m;
+  const int64_t base = tile * (kRandBlock * kRandItems) + threadIdx.x;
   int32_t v[kRandItems];
 #pragma unroll
   for (int it = 0; it < kRandItems; ++it) {
     const int64_t k = base + it * kRandBlock;
-    v[it] = k < m ? stream_load(idx + k) : 0;
+    v[it] = k < m ? stream_load(a.idx + k) : 0;
   }
 #pragma unroll
   for (int it = 0; it < kRandItems; ++it) {
     const int64_t k = base + it * kRandBlock;
     if (k >= m) break;
-    int64_t lo = 0, cnt = n;
+    int64_t lo = 0, cnt = a.n;
     if constexpr (BATCHED) {
-      const uint32_t b = mesh_of(elem_off, nmesh, k / arity, elem_tab);
-      lo = vtx_off[b];
-      cnt = vtx_off[b + 1] - lo;
+      const uint32_t b = mesh_of(a.elem_off, a.nmesh, k / a.arity, a.elem_tab);
+      lo = a.vtx_off[b];
+      cnt = a.vtx_off[b + 1] - lo;
     }
-    if (v[it] < 0 || v[it] >= cnt || lo < 0 || lo + v[it] >= n) {
-      atomicMax(status, kErrIndex);
+    if (v[it] < 0 || v[it] >= cnt || lo < 0 || lo + v[it] >= a.n) {
+      atomicMax(a.status, kErrIndex);
     } else {
-      used[lo + v[it]] = 1;
+      a.used[lo + v[it]] = 1;
     }
   }
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(kRandBlock) void k_mark_used(MarkArgs a) {
+  mark_used_tile<BATCHED>(a, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -343,7 +356,7 @@ __global__ __launch_bounds__(kRandBlock) void k_remap(const int32_t* idx, int64_
                                                       const int32_t* __restrict__ elem_tab,
                                                       const int64_t* __restrict__ live_elems,
                                                       const int32_t* __restrict__ old2new, int32_t* out_idx) {
-  if (live_elems) m = min(m, *live_elems * arity);  // see k_mark_used
+  if (live_elems) m = min(m, *live_elems * arity);  // see MarkArgs
   const int64_t base = int64_t(blockIdx.x) * (kRandBlock * kRandItems) + threadIdx.x;
   int64_t src[kRandItems];
 #pragma unroll

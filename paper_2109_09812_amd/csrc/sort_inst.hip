@@ -49,6 +49,40 @@ void launch_hist(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) 
   if (grid > 0) hipLaunchKernelGGL((k_histogram<K, D, B, GROUPS>), dim3(grid), dim3(B), 0, s, vtx, n, hist);
 }
 
+// Every block of the fused launch holds the histogram's LDS; beyond this size
+// it would cut the number of marking waves a CU can hold.
+constexpr int kFusedHistLds = 16 * 1024;
+
+template <int D>
+bool mark_hist_applies(int64_t n, int64_t m) {
+  constexpr int P = (32 * K + D - 1) / D;
+  if (P * (1 << D) * 4 > kFusedHistLds || n <= 0 || m <= 0) return false;
+  constexpr int R = 4 / gcd4(K);
+  const int64_t ht = (n + int64_t(kRandBlock) * 4 * R - 1) / (int64_t(kRandBlock) * 4 * R);
+  const int64_t mt = (m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
+  return ht + mt <= INT32_MAX;
+}
+
+template <int D>
+void launch_mark_hist(const MarkArgs& ma, bool batched, const uint32_t* vtx, int64_t n, uint32_t* hist,
+                      hipStream_t s) {
+  constexpr int B = kRandBlock, GROUPS = 4;
+  constexpr int P = (32 * K + D - 1) / D;
+  if constexpr (P * (1 << D) * 4 <= kFusedHistLds) {
+    if (!mark_hist_applies<D>(n, ma.m)) return;
+    constexpr int R = 4 / gcd4(K);
+    const int64_t per_block = int64_t(B) * GROUPS * R;
+    const int64_t ht = (n + per_block - 1) / per_block;
+    const int64_t mt = (ma.m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
+    if (batched)
+      hipLaunchKernelGGL((k_mark_histogram<K, D, B, GROUPS, true>), dim3(ht + mt), dim3(B), 0, s, ma, vtx, n,
+                         hist, ht, mt);
+    else
+      hipLaunchKernelGGL((k_mark_histogram<K, D, B, GROUPS, false>), dim3(ht + mt), dim3(B), 0, s, ma, vtx, n,
+                         hist, ht, mt);
+  }
+}
+
 template <int D>
 void launch_mesh_hist(const int64_t* off, int32_t nmesh, int32_t passes, uint32_t* hist, hipStream_t s) {
   if (nmesh <= 0 || passes <= 0) return;
@@ -78,6 +112,8 @@ SortVariant make() {
   v.ipt = IPT;
   v.pass = &launch_pass<D, BLOCK, IPT>;
   v.hist = &launch_hist<D>;
+  v.mark_hist_applies = &mark_hist_applies<D>;
+  v.mark_hist = &launch_mark_hist<D>;
   v.mesh_hist = &launch_mesh_hist<D>;
   v.scan = &launch_scan<D>;
   v.flag_scan = &launch_flag_scan;

@@ -151,6 +151,48 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t* __restrict_
     if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
+// One chunk of BLOCK * GROUPS record groups into the block's LDS histograms
+// `s_h` ([P * RADIX], zeroed), then added to `hist`: the histogram half of
+// the fused used-marking launch, where every chunk has its own workgroup.
+template <int K, int D, int BLOCK, int GROUPS>
+__device__ __forceinline__ void histogram_chunk(const uint32_t* __restrict__ vtx, int64_t n,
+                                                uint32_t* __restrict__ hist, uint32_t* s_h, int64_t chunk) {
+  constexpr int RADIX = 1 << D;
+  constexpr int P = (32 * K + D - 1) / D;
+  constexpr int R = 4 / gcd4(K);
+  constexpr int GW = R * K;
+  uint32_t last[P], run[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
+  const bool vec = (reinterpret_cast<uintptr_t>(vtx) & 15) == 0;
+  for (int it = 0; it < GROUPS; ++it) {
+    const int64_t g = chunk * (BLOCK * GROUPS) + int64_t(it) * BLOCK + threadIdx.x;
+    const int64_t r0 = g * R;
+    if (r0 >= n) break;
+    uint32_t w[GW];
+    if (vec && r0 + R <= n) {
+      const uint4* p4 = reinterpret_cast<const uint4*>(vtx + r0 * K);
+#pragma unroll
+      for (int q = 0; q < GW / 4; ++q) {
+        const uint4 x = p4[q];
+        w[4 * q] = x.x; w[4 * q + 1] = x.y; w[4 * q + 2] = x.z; w[4 * q + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < GW; ++q) w[q] = (r0 * K + q < n * K) ? vtx[r0 * K + q] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r0 + r < n) hist_record<K, D>(w + r * K, s_h, last, run);
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P * RADIX; i += BLOCK)
+    if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
 // Histograms of the mesh-id passes of a batch: mesh b contributes its vertex
 // count to digit (b >> shift_q) of mesh pass q.
 template <int D>
