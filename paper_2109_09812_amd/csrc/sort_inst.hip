@@ -40,9 +40,13 @@ void launch_pass(const SortPassArgs& a, int mode, bool wide, int64_t grid, hipSt
     launch_pass_w<D, BLOCK, IPT, false>(a, mode, grid, s);
 }
 
+// Record groups per thread of a histogram workgroup (a chunk is 256 threads
+// times this many groups).
+constexpr int kHistGroups = 4;
+
 template <int D>
 void launch_hist(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) {
-  constexpr int B = 256, GROUPS = 4;
+  constexpr int B = 256, GROUPS = kHistGroups;
   constexpr int R = 4 / gcd4(K);
   const int64_t per_block = int64_t(B) * GROUPS * R;
   const int64_t grid = (n + per_block - 1) / per_block;
@@ -57,8 +61,8 @@ template <int D>
 bool mark_hist_applies(int64_t n, int64_t m) {
   constexpr int P = (32 * K + D - 1) / D;
   if (P * (1 << D) * 4 > kFusedHistLds || n <= 0 || m <= 0) return false;
-  constexpr int R = 4 / gcd4(K);
-  const int64_t ht = (n + int64_t(kRandBlock) * 4 * R - 1) / (int64_t(kRandBlock) * 4 * R);
+  constexpr int64_t per_block = int64_t(kRandBlock) * kHistGroups * (4 / gcd4(K));
+  const int64_t ht = (n + per_block - 1) / per_block;
   const int64_t mt = (m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
   return ht + mt <= INT32_MAX;
 }
@@ -66,7 +70,7 @@ bool mark_hist_applies(int64_t n, int64_t m) {
 template <int D>
 void launch_mark_hist(const MarkArgs& ma, bool batched, const uint32_t* vtx, int64_t n, uint32_t* hist,
                       hipStream_t s) {
-  constexpr int B = kRandBlock, GROUPS = 4;
+  constexpr int B = kRandBlock, GROUPS = kHistGroups;
   constexpr int P = (32 * K + D - 1) / D;
   if constexpr (P * (1 << D) * 4 <= kFusedHistLds) {
     if (!mark_hist_applies<D>(n, ma.m)) return;
