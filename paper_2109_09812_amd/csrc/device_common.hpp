@@ -121,6 +121,45 @@ struct Control {
   int64_t num_used;     // U of a batch (all meshes)
 };
 
+// The two element buffers of the LSD sort. A pass whose digit is the same
+// for every element (read off the digit histograms) would not reorder
+// anything and moves no data, so which buffer holds the elements before a
+// pass depends on how many passes before it moved them. `plan` holds
+// 2 * passes + 1 words: dead(p) = plan[passes + 1 + p] is 1 if one digit
+// holds every element in pass p (written with the bucket offsets); the first
+// pass, which reads the caller's records and always runs, then fills in
+// plan[p], 1 <= p < passes: bit 0 = buffer that pass p reads (it writes the
+// other), bit 1 = pass p is skipped; and plan[passes] = buffer holding the
+// sorted elements.
+struct SortBuffers {
+  uint32_t* buf[2];
+  uint32_t* plan;
+  int32_t passes;
+
+  // plan[p], the same for every lane (kept in scalar registers)
+  __device__ __forceinline__ uint32_t entry(int p) const {
+    return __builtin_amdgcn_readfirstlane(plan[p]);
+  }
+  __device__ __forceinline__ bool skipped(int p) const { return (entry(p) & 2u) != 0u; }
+  __device__ __forceinline__ uint32_t* input_of(int p) const { return (entry(p) & 1u) ? buf[1] : buf[0]; }
+  __device__ __forceinline__ uint32_t* output_of(int p) const { return (entry(p) & 1u) ? buf[0] : buf[1]; }
+  // after the last pass: the sorted elements, and the other buffer
+  __device__ __forceinline__ uint32_t* sorted() const { return input_of(passes); }
+  __device__ __forceinline__ uint32_t* spare() const { return output_of(passes); }
+};
+
+// Fills in plan[1 .. passes] from the dead flags; one thread.
+__device__ __forceinline__ void write_sort_plan(const SortBuffers& b) {
+  const uint32_t* dead = b.plan + b.passes + 1;
+  uint32_t in = 0;  // the first pass writes buf[0]
+  for (int p = 1; p < b.passes; ++p) {
+    const bool skip = dead[p] != 0u;
+    b.plan[p] = in | (skip ? 2u : 0u);
+    if (!skip) in ^= 1u;
+  }
+  b.plan[b.passes] = in;
+}
+
 // Exclusive prefix over tiles [0, tile) for one bin. The walk reads W
 // predecessor words per step (tile-1 .. tile-W) with independent loads, adds
 // aggregates until it meets an inclusive prefix, and re-polls from the first

@@ -32,15 +32,16 @@ __global__ void k_fill_zero(uint4* __restrict__ p, int64_t n16, int32_t* status,
 // Batch epilogue: out_off[b] = number of used groups of meshes < b, read
 // from cmap at the first sorted position of mesh b (a head, since heads
 // break at mesh starts).
-__global__ void k_batch_offsets(const int64_t* __restrict__ vtx_off, int32_t nmesh,
-                                const uint2* __restrict__ pairs, const int32_t* __restrict__ cmap,
-                                const Control* ctl, const int64_t* __restrict__ total_used,
-                                int64_t n, int64_t* __restrict__ out_off) {
+__global__ void k_batch_offsets(const int64_t* __restrict__ vtx_off, int32_t nmesh, SortBuffers bufs,
+                                const int32_t* __restrict__ cmap, const Control* ctl,
+                                const int64_t* __restrict__ total_used, int64_t n,
+                                int64_t* __restrict__ out_off) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nmesh) return;
   const int64_t p = vtx_off[b];
   int64_t r = *total_used;
   if (b < nmesh && p >= 0 && p < n) {
+    const uint2* pairs = reinterpret_cast<const uint2*>(bufs.spare());
     const uint32_t g = pairs[p].x;
     if (int64_t(g) < ctl->num_groups) {
       const int32_t c = cmap[g];
@@ -162,8 +163,8 @@ struct Layout {
   int K = 0, S = 0, P_key = 0, P_mesh = 0;
   int64_t tiles_sort = 0, tiles_scan = 0;
   // zeroed region
-  size_t ctl = 0, counters = 0, hist = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0, used_v = 0,
-         used_g = 0, zero_end = 0;
+  size_t ctl = 0, counters = 0, hist = 0, plan = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0,
+         used_v = 0, used_g = 0, zero_end = 0;
   int64_t tiles_elem = 0;
   // scratch
   size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, total = 0;
@@ -189,6 +190,7 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.ctl = off;      off = align_up(off + sizeof(Control));
   L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + 3));
   L.hist = off;     off = align_up(off + sizeof(uint32_t) * size_t(P) * size_t(v.radix()));
+  L.plan = off;     off = align_up(off + sizeof(uint32_t) * size_t(2 * P + 1));  // SortBuffers::plan
   // sort look-back: tiles x radix 64-bit words, or two alternating buffers of
   // 32-bit words in the same bytes; flag scan and compaction have their own
   const int64_t lb_words = std::max<int64_t>(L.tiles_sort * v.radix(), 1);
@@ -335,6 +337,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
   Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
   uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint32_t* plan = reinterpret_cast<uint32_t*>(ws + L.plan);
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
   const bool wide = wide_lookback(n, tuning);
@@ -375,17 +378,16 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
       v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
     }
     prof_mark("scan_buckets", s);
-    v.scan(hist, L.P_key, s);
-    const uint32_t* src = static_cast<const uint32_t*>(vtx);
-    int cur = 0;
+    v.scan(hist, L.P_key, n, plan + L.P_key + 1, s);
+    const SortBuffers sb{{buf[0], buf[1]}, plan, L.P_key};
     for (int p = 0; p < L.P_key; ++p) {
       SortPassArgs a{};
-      a.src = src;
-      a.dst = buf[cur];
+      a.vtx = static_cast<const uint32_t*>(vtx);
+      a.bufs = sb;
+      a.pass = p;
       a.used = used_v;
       a.bucket_base = hist + size_t(p) * v.radix();
       a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
-      a.lookback_next = lb32[(p + 1) & 1];
       a.tile_counter = claimed ? counters + p : nullptr;
       a.ctl = ctl;
       a.status = status;
@@ -394,14 +396,11 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
       a.tag = uint32_t(p + 1);
       prof_mark(p == 0 ? "onesweep_first" : "onesweep", s);
       v.pass(a, p == 0 ? kPassFirst : kPassKey, wide, L.tiles_sort, s);
-      src = buf[cur];
-      cur ^= 1;
     }
     // Step 2 flags + prefix sum, Step 3/4 scatters
     FlagScanArgs f{};
-    f.sorted = src;
+    f.bufs = sb;
     f.n = n;
-    f.pairs = reinterpret_cast<uint2*>(buf[cur]);  // the buffer the last pass read from
     f.uniq = uniq;
     f.rep = rep;
     f.used_g = used_g;
@@ -432,7 +431,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       f.pairs, cmap, n, nullptr, nullptr, 0, nullptr, old2new);
+                       sb, cmap, n, nullptr, nullptr, 0, nullptr, old2new);
   }
   // Step 4: remap the index array
   if (m > 0) {
@@ -587,6 +586,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
   uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint32_t* plan = reinterpret_cast<uint32_t*>(ws + L.plan);
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
   const bool wide = wide_lookback(n, tuning);
@@ -640,17 +640,16 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     prof_mark("mesh_histogram", s);
     v.mesh_hist(vtx_offsets, num_meshes, L.P_mesh, hist + size_t(L.P_key) * v.radix(), s);
     prof_mark("scan_buckets", s);
-    v.scan(hist, P, s);
-    const uint32_t* src = static_cast<const uint32_t*>(vtx);
-    int cur = 0;
+    v.scan(hist, P, n, plan + P + 1, s);
+    const SortBuffers sb{{buf[0], buf[1]}, plan, P};
     for (int p = 0; p < P; ++p) {
       SortPassArgs a{};
-      a.src = src;
-      a.dst = buf[cur];
+      a.vtx = static_cast<const uint32_t*>(vtx);
+      a.bufs = sb;
+      a.pass = p;
       a.used = used_v;
       a.bucket_base = hist + size_t(p) * v.radix();
       a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
-      a.lookback_next = lb32[(p + 1) & 1];
       a.tile_counter = claimed ? counters + p : nullptr;
       a.ctl = ctl;
       a.status = status;
@@ -669,13 +668,10 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
       }
       prof_mark(mode == kPassFirst ? "onesweep_first" : mode == kPassMesh ? "onesweep_mesh" : "onesweep", s);
       v.pass(a, mode, wide, L.tiles_sort, s);
-      src = buf[cur];
-      cur ^= 1;
     }
     FlagScanArgs f{};
-    f.sorted = src;
+    f.bufs = sb;
     f.n = n;
-    f.pairs = reinterpret_cast<uint2*>(buf[cur]);  // the buffer the last pass read from
     f.uniq = uniq;
     f.rep = rep;
     f.used_g = used_g;
@@ -708,12 +704,11 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("batch_offsets", s);
     hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets,
-                       num_meshes, static_cast<const uint2*>(f.pairs), static_cast<const int32_t*>(cmap),
-                       static_cast<const Control*>(ctl), static_cast<const int64_t*>(&ctl->num_used), n,
-                       out_vtx_offsets);
+                       num_meshes, sb, static_cast<const int32_t*>(cmap), static_cast<const Control*>(ctl),
+                       static_cast<const int64_t*>(&ctl->num_used), n, out_vtx_offsets);
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<true>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       f.pairs, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes,
+                       sb, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes,
                        static_cast<const int32_t*>(vtab), old2new);
     if (new2old) {
       prof_mark("localize_new2old", s);
@@ -723,7 +718,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   } else {
     prof_mark("batch_offsets", s);
     hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets,
-                       num_meshes, static_cast<const uint2*>(nullptr), static_cast<const int32_t*>(cmap),
+                       num_meshes, SortBuffers{{nullptr, nullptr}, nullptr, 0}, static_cast<const int32_t*>(cmap),
                        static_cast<const Control*>(ctl), static_cast<const int64_t*>(&ctl->num_used), n,
                        out_vtx_offsets);
   }

@@ -59,8 +59,9 @@ struct SortVariant {
   // digit histograms of the mesh-id passes of a batch
   void (*mesh_hist)(const int64_t* off, int32_t nmesh, int32_t passes, uint32_t* hist,
                     hipStream_t) = nullptr;
-  // per-pass exclusive scan of the histograms
-  void (*scan)(uint32_t* hist, int32_t passes, hipStream_t) = nullptr;
+  // per-pass exclusive scan of the histograms, and the passes whose digit
+  // is the same for all n elements (dead[p] = 1)
+  void (*scan)(uint32_t* hist, int32_t passes, int64_t n, uint32_t* dead, hipStream_t) = nullptr;
   // run-head flags + prefix sum + scatters over the sorted elements
   void (*flag_scan)(const FlagScanArgs&, bool batched, int64_t grid, hipStream_t) = nullptr;
 

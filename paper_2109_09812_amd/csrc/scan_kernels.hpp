@@ -76,9 +76,9 @@ __global__ __launch_bounds__(kRandBlock) void k_mark_used(MarkArgs a) {
 // (gid(i), original id) at its sorted position and marks the group used if
 // the vertex is referenced. The last tile stores G.
 struct FlagScanArgs {
-  const uint32_t* sorted;  // [n][K+1]
+  SortBuffers bufs;        // sorted(): [n][K+1] elements; spare(): receives the
+                           // [n] (group id, original id) pairs in sorted order
   int64_t n;
-  uint2* pairs;            // [n] (group id, original id) in sorted order
   uint32_t* uniq;          // [G][K] group records
   int32_t* rep;            // [G] smallest original id of the group
   uint8_t* used_g;         // [G] zeroed; 1 = some copy referenced
@@ -102,9 +102,12 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
   __shared__ uint32_t s_prefix;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const uint32_t fin = a.bufs.entry(a.bufs.passes);  // requested before the barrier
   const uint32_t tile = claim_tile(a.tile_counter, &s_tile);
   const int64_t n = a.n;
   const int64_t wave_base = int64_t(tile) * TILE + int64_t(wave) * (kWave * IPT) + lane;
+  const uint32_t* sorted = a.bufs.buf[fin & 1u];
+  uint2* pairs = reinterpret_cast<uint2*>(a.bufs.buf[(fin & 1u) ^ 1u]);
 
   uint32_t id[IPT];
   uint32_t incl[IPT];   // heads at or before this element within the wave's (j, lane) order
@@ -116,13 +119,13 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
   {
     const int64_t p0 = wave_base - lane - 1;
 #pragma unroll
-    for (int w = 0; w < K; ++w) carry[w] = (p0 >= 0 && p0 < n) ? a.sorted[p0 * S + w] : 0u;
+    for (int w = 0; w < K; ++w) carry[w] = (p0 >= 0 && p0 < n) ? sorted[p0 * S + w] : 0u;
   }
   uint32_t e[IPT][S];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int64_t pos = wave_base + j * kWave;
-    if (pos < n) load_words<S>(a.sorted + pos * S, e[j]);
+    if (pos < n) load_words<S>(sorted + pos * S, e[j]);
     else {
 #pragma unroll
       for (int w = 0; w < S; ++w) e[j][w] = 0;
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
       a.rep[g] = int32_t(org);
     }
     if (id[j] & 0x80000000u) a.used_g[g] = 1;
-    a.pairs[pos] = make_uint2(g, org);
+    pairs[pos] = make_uint2(g, org);
     if (pos == n - 1) a.ctl->num_groups = int64_t(g) + 1;
   }
 }
@@ -292,17 +295,19 @@ __global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
 }
 
 // Step 4's map: old2new[org] = new id of the group of each sorted element
-// (-1 if the group is unused), a scatter from sorted positions; the cmap
-// reads follow the non-decreasing group ids. For a batch the new id is made
+// (-1 if the group is unused), a scatter from the (group id, original id)
+// pairs that the flag scan left in the spare sort buffer; the cmap reads
+// follow the non-decreasing group ids. For a batch the new id is made
 // mesh-local with the mesh's output offset.
 template <bool BATCHED>
-__global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(const uint2* __restrict__ pairs,
+__global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(SortBuffers bufs,
                                                                 const int32_t* __restrict__ cmap, int64_t n,
                                                                 const int64_t* __restrict__ vtx_off,
                                                                 const int64_t* __restrict__ out_off,
                                                                 int32_t nmesh, const int32_t* __restrict__ vtx_tab,
                                                                 int32_t* __restrict__ old2new) {
   constexpr int TILE = kRandBlock * kScatterItems;
+  const uint2* __restrict__ pairs = reinterpret_cast<const uint2*>(bufs.spare());
   __shared__ int32_t s_cmap[TILE];
   __shared__ uint32_t s_g[2];
   const int64_t t0 = int64_t(blockIdx.x) * TILE;

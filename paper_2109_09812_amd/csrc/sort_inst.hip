@@ -95,8 +95,8 @@ void launch_mesh_hist(const int64_t* off, int32_t nmesh, int32_t passes, uint32_
 }
 
 template <int D>
-void launch_scan(uint32_t* hist, int32_t passes, hipStream_t s) {
-  if (passes > 0) hipLaunchKernelGGL((k_scan_buckets<D, 256>), dim3(passes), dim3(256), 0, s, hist);
+void launch_scan(uint32_t* hist, int32_t passes, int64_t n, uint32_t* dead, hipStream_t s) {
+  if (passes > 0) hipLaunchKernelGGL((k_scan_buckets<D, 256>), dim3(passes), dim3(256), 0, s, hist, n, dead);
 }
 
 void launch_flag_scan(const FlagScanArgs& a, bool batched, int64_t grid, hipStream_t s) {

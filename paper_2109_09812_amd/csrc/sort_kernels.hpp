@@ -17,15 +17,15 @@ namespace mrx {
 enum PassMode : int { kPassFirst = 0, kPassKey = 1, kPassMesh = 2 };
 
 struct SortPassArgs {
-  const uint32_t* src;          // first pass: vertex records (K words); else elements (K+1 words)
-  uint32_t* dst;                // elements (K+1 words)
+  const uint32_t* vtx;          // first pass: vertex records (K words)
+  SortBuffers bufs;             // elements (K+1 words); the first pass writes buf[0] and the plan
   const uint8_t* used;          // first pass: 1 if some index entry references the vertex
-  const uint32_t* bucket_base;  // [RADIX] start of each digit's bucket in dst
+  const uint32_t* bucket_base;  // [RADIX] start of each digit's bucket in the output
   // Look-back words, [tiles][RADIX]: LbTagged words (wide launches), or
-  // LbCompact words in `lookback` with `lookback_next` the buffer of the
-  // next launch, which this launch clears.
+  // LbCompact words. These alternate between two buffers of tiles * RADIX
+  // words, the second right after the first (pass p uses buffer p % 2); each
+  // launch clears its rows of the buffer the next pass uses.
   void* lookback;
-  uint32_t* lookback_next;
   uint32_t* tile_counter;
   Control* ctl;
   int32_t* status;
@@ -40,7 +40,19 @@ struct SortPassArgs {
   int32_t shift;                // bit offset of the digit inside word_lo (mesh passes: inside the mesh id)
   int64_t n;
   uint32_t tag;
+  int32_t pass;                 // index of this pass
 };
+// Kept within 256 bytes: a larger argument block measurably raised the
+// register count of the pass kernels on gfx950 (e.g. 125 -> 138 VGPRs for
+// 512 x 16 tiles, one wave fewer per SIMD).
+static_assert(sizeof(SortPassArgs) <= 256, "pass arguments outgrew 256 bytes");
+
+// LbCompact buffer of the pass after `pass`: the other half of the pair
+// (tiles = the grid size).
+__device__ __forceinline__ uint32_t* lookback_next_of(void* lookback, int32_t pass, int64_t tiles, int radix) {
+  uint32_t* lb = static_cast<uint32_t*>(lookback);
+  return (pass & 1) ? lb - tiles * radix : lb + tiles * radix;
+}
 
 // (word_hi:word_lo) >> shift, masked to D bits, with the words chosen by masks.
 template <int D, int K, int N>
@@ -207,21 +219,27 @@ __global__ void k_mesh_histogram(const int64_t* __restrict__ off, int32_t nmesh,
     atomicAdd(&hist[q * RADIX + ((uint32_t(b) >> (q * D)) & (RADIX - 1))], cnt);
 }
 
-// Exclusive scan of each pass's RADIX counts, in place (one block per pass).
+// Exclusive scan of each pass's RADIX counts, in place (one block per pass),
+// and dead[p] = 1 if one digit holds all n elements in pass p.
 template <int D, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_scan_buckets(uint32_t* __restrict__ hist) {
+__global__ __launch_bounds__(BLOCK) void k_scan_buckets(uint32_t* __restrict__ hist, int64_t n,
+                                                        uint32_t* __restrict__ dead) {
   constexpr int RADIX = 1 << D;
   constexpr int BPT = (RADIX + BLOCK - 1) / BLOCK;
   __shared__ uint32_t s_wave[BLOCK / kWave];
   uint32_t* h = hist + int64_t(blockIdx.x) * RADIX;
   uint32_t c[BPT];
   uint32_t sum = 0;
+  int all = 0;
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const int bin = threadIdx.x * BPT + k;
     c[k] = bin < RADIX ? h[bin] : 0u;
     sum += c[k];
+    all |= int64_t(c[k]) == n;
   }
+  all = __syncthreads_or(all);
+  if (threadIdx.x == 0) dead[blockIdx.x] = all ? 1u : 0u;
   uint32_t total;
   uint32_t run = block_exclusive_scan<BLOCK>(sum, s_wave, &total);
 #pragma unroll
@@ -274,8 +292,26 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
+  // This pass's plan entry is requested first and examined after the LDS
+  // set-up and the block barrier below, so its latency is hidden.
+  const uint32_t entry = MODE == kPassFirst ? 0u : a.bufs.entry(a.pass);
+  if constexpr (MODE == kPassFirst) {
+    if (blockIdx.x == 0 && tid == 0) write_sort_plan(a.bufs);
+  }
   for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_hist[i] = 0;
   const uint32_t tile = claim_tile(a.tile_counter, &s_tile);  // synchronises the block
+  if constexpr (MODE != kPassFirst) {
+    // A pass with a single live digit would leave the order as it is: it
+    // moves nothing, and only clears its row of the next pass's look-back
+    // buffer.
+    if (entry & 2u) {
+      if constexpr (!WIDE)
+        for (int bin = tid; bin < RADIX; bin += BLOCK)
+          lb_store(lookback_next_of(a.lookback, a.pass, gridDim.x, RADIX) + int64_t(tile) * RADIX + bin, 0u);
+      return;
+    }
+  }
+  const uint32_t* const src = MODE == kPassFirst ? a.vtx : a.bufs.buf[entry & 1u];
   const int64_t tile_base = int64_t(tile) * TILE;
   const int64_t n = a.n;
   const int valid_count = int(min(int64_t(TILE), n - tile_base));
@@ -321,11 +357,11 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
     if (pos < n) {
       if constexpr (MODE == kPassFirst) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[j][k] = a.src[pos * K + k];
+        for (int k = 0; k < K; ++k) v[j][k] = src[pos * K + k];
         const bool used = (IPT % 4 == 0) ? s_used[j * kWave + lane] != 0 : a.used[pos] != 0;
         v[j][K] = uint32_t(pos) | (used ? 0x80000000u : 0u);
       } else {
-        load_words<S>(a.src + pos * S, v[j]);
+        load_words<S>(src + pos * S, v[j]);
       }
     } else {
 #pragma unroll
@@ -392,7 +428,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
         s_hist[w * RADIX + bin] = run;
         run += c;
       }
-      if constexpr (!WIDE) lb_store(a.lookback_next + int64_t(tile) * RADIX + bin, 0u);
+      if constexpr (!WIDE)
+        lb_store(lookback_next_of(a.lookback, a.pass, gridDim.x, RADIX) + int64_t(tile) * RADIX + bin, 0u);
       const uint32_t gend = bin + 1 < RADIX ? a.bucket_base[bin + 1] : uint32_t(n);
       live[k] = gend != a.bucket_base[bin];
       if (live[k]) {
@@ -462,9 +499,10 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   }
 
   // ---- scatter: consecutive q of one digit go to consecutive addresses
+  uint32_t* const out = a.bufs.buf[MODE == kPassFirst ? 0u : (entry & 1u) ^ 1u];
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
-    if (int64_t(opos[r]) < n) store_words<S>(a.dst + int64_t(opos[r]) * S, v[r]);
+    if (int64_t(opos[r]) < n) store_words<S>(out + int64_t(opos[r]) * S, v[r]);
   }
 }
 

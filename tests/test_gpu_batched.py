@@ -45,6 +45,35 @@ def test_batched_matches_per_mesh_oracle(meshes, hi, seed):
     check_batch(b, res)
 
 
+def test_batched_with_skipped_passes():
+    """Key passes whose digit is the same in every mesh are skipped in a
+    batch too (the mesh-id passes never are here: 5 meshes)."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(78)
+    sizes = [3_001, 0, 17_000, 5, 40_000]
+    n = sum(sizes)
+    vtx = np.full((n, 3), 0x3F000000, np.uint32)
+    vtx[:, 1] = rng.integers(0, 9, n).astype(np.uint32) << np.uint32(16)   # one live key pass
+    vo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    idx_parts, eo = [], [0]
+    for sz in sizes:
+        e = sz // 3
+        idx_parts.append(rng.integers(0, max(sz, 1), size=(e, 3)).astype(np.int32))
+        eo.append(eo[-1] + e)
+    idx = np.concatenate(idx_parts)
+    eo = np.array(eo, np.int64)
+    _say("batch with skipped passes", n, "vertices")
+    for t in (None, (0, 0, 0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES)):
+        res = mrx.reindex_mesh_batched(torch.from_numpy(vtx.view(np.int32)).to(DEV), torch.from_numpy(vo).to(DEV),
+                                       torch.from_numpy(idx).to(DEV), torch.from_numpy(eo).to(DEV), tuning=t)
+        ov, ooff, oi, o2n, n2o = oracle.reindex_batched(vtx, idx, vo, eo)
+        assert np.array_equal(res.out_vtx_offsets.cpu().numpy(), ooff)
+        assert np.array_equal(res.out_vtx.cpu().numpy().view(np.uint32), ov)
+        assert np.array_equal(res.out_idx.cpu().numpy(), oi)
+        assert np.array_equal(res.old2new.cpu().numpy(), o2n)
+        assert np.array_equal(res.new2old.cpu().numpy(), n2o)
+
+
 def test_cross_mesh_vertices_never_merge():
     import paper_2109_09812_amd as mrx
     one = meshgen.batched(1, 500, 501, 0.05, 31)

@@ -177,6 +177,35 @@ def test_every_record_width_every_tuning():
         assert_parity(*meshgen.random_mesh(37, 200_003, 3, k, 20, 4_900 + k), name=f"many elements {k}")
 
 
+def _few_live_bytes(n, live, rng):
+    """Records of three words, all equal except the byte of each LSD pass in
+    ``live`` (pass p = byte p % 4 of word 2 - p // 4), which takes 7 values."""
+    vtx = np.full((n, 3), 0x3F000000, np.uint32)
+    for p in live:
+        word, shift = 2 - p // 4, 8 * (p % 4)
+        vtx[:, word] &= np.uint32(~(0xFF << shift) & 0xFFFFFFFF)
+        vtx[:, word] |= rng.integers(0, 7, n).astype(np.uint32) << np.uint32(shift)
+    return vtx
+
+
+def test_single_digit_passes_are_skipped():
+    """A pass whose digit is the same for every record moves nothing; the
+    element buffers then alternate on the device. One, two and three live
+    passes (odd and even numbers skipped), the last pass alone, only the
+    first, every record equal; each under every look-back and tile-order
+    flag."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(77)
+    n = 50_003
+    idx = rng.integers(0, n, size=(20_000, 3)).astype(np.int32)
+    both = mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES
+    flag_sets = (0, mrx.MRX_TUNING_WIDE_LOOKBACK, mrx.MRX_TUNING_CLAIMED_TILES, both)
+    for live in ([6], [2, 9], [1, 5, 10], [11], [0], []):
+        vtx = _few_live_bytes(n, live, rng)
+        for fl in flag_sets:
+            assert_parity(vtx, idx, tuning=(0, 0, 0, fl), name=f"live passes {live} flags {fl}")
+
+
 def test_tuning_flags_match():
     """64-bit look-back words (forced here; automatic from 2^30 vertices on)
     and counter-claimed tiles give the same result as the defaults, in every
