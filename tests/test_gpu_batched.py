@@ -159,6 +159,36 @@ def test_graph_replays_with_new_contents():
         _ = (tensors[0].float() * 2).sum().item()
 
 
+def test_graph_replays_with_changing_skipped_passes():
+    """The pass plan is worked out on the device in every replay: contents
+    that alternate between records with several single-digit passes and
+    records with none must all come out exact."""
+    import paper_2109_09812_amd as mrx
+    base = meshgen.batched(30, 100, 6000, 0.05, 88)
+    rng = np.random.default_rng(9)
+    n = base.vtx.shape[0]
+    flat = np.full((n, 3), 0x3F000000, np.uint32)
+    flat[:, 1] = rng.integers(0, 5, n).astype(np.uint32) << np.uint32(8)     # one live key pass
+    few = meshgen.Batch(flat.view(np.float32), base.idx, base.vtx_offsets, base.elem_offsets, None, "few")
+    tensors = to_dev(base)
+    _say("capture graph (skipped passes)")
+    gr = mrx.GraphedBatchedReindexer(*tensors)
+    for rep, b in enumerate([few, base, few, base]):
+        _say("replay", rep, b.name)
+        tensors[0].copy_(torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)))
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        res = gr.result()
+        ov, ooff, oi, o2n, n2o = oracle.reindex_batched(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
+        assert np.array_equal(res.out_vtx_offsets.cpu().numpy(), ooff)
+        assert np.array_equal(res.out_vtx.cpu().numpy().view(np.uint32), ov)
+        assert np.array_equal(res.out_idx.cpu().numpy(), oi)
+        assert np.array_equal(res.old2new.cpu().numpy(), o2n)
+        assert np.array_equal(res.new2old.cpu().numpy(), n2o)
+        _ = (tensors[0].float() * 2).sum().item()
+
+
 def test_batched_tuning_flags():
     import paper_2109_09812_amd as mrx
     b = meshgen.batched(300, 100, 5000, 0.05, 616)
