@@ -263,7 +263,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_buckets(uint32_t* __restrict__ h
 // block scan gives each digit's start inside the tile, and a decoupled
 // look-back over preceding tiles (one word per (tile, digit)) gives the
 // digit's global offset. Elements are reordered through LDS into digit
-// order, one 32-bit word plane at a time, so each thread writes runs of
+// order, two 32-bit word planes (one 8-byte slot per element) at a time
+// where LDS allows, so each thread writes runs of
 // consecutive addresses.
 template <int K, int D, int BLOCK, int IPT, int MODE, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   __shared__ uint32_t s_hist[WAVES * RADIX];
   __shared__ uint32_t s_start[RADIX];
   __shared__ uint32_t s_base[RADIX];
-  __shared__ uint32_t s_buf[NBUF][TILE];
+  __shared__ __align__(16) uint32_t s_buf[NBUF][TILE];
   __shared__ uint16_t s_dig[TILE];
   __shared__ uint32_t s_wave[WAVES];
   __shared__ uint32_t s_tile;
@@ -461,19 +462,54 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
     }
   }
 
-  // ---- reorder one word plane at a time through LDS (double-buffered)
+  // ---- reorder through LDS: two word planes at a time (8-byte slots) when
+  // two planes fit, else one plane at a time
+  if constexpr (NBUF == 2) {
+    uint2* buf2 = reinterpret_cast<uint2*>(&s_buf[0][0]);
 #pragma unroll
-  for (int w = 0; w < S; ++w) {
-    uint32_t* buf = s_buf[w % NBUF];
-    if (NBUF == 1 && w > 0) __syncthreads();  // previous plane fully read
+    for (int w = 0; w + 1 < S; w += 2) {
+      if (w > 0) __syncthreads();  // previous pair fully read
 #pragma unroll
-    for (int j = 0; j < IPT; ++j)
-      if ((wave_base + j * kWave) < n) buf[rank[j]] = v[j][w];
-    __syncthreads();
+      for (int j = 0; j < IPT; ++j)
+        if ((wave_base + j * kWave) < n) buf2[rank[j]] = make_uint2(v[j][w], v[j][w + 1]);
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      const int q = r * BLOCK + tid;
-      if (q < valid_count) v[r][w] = buf[q];
+      for (int r = 0; r < IPT; ++r) {
+        const int q = r * BLOCK + tid;
+        if (q < valid_count) {
+          const uint2 x = buf2[q];
+          v[r][w] = x.x;
+          v[r][w + 1] = x.y;
+        }
+      }
+    }
+    if constexpr (S % 2 == 1) {
+      uint32_t* buf = &s_buf[0][0];
+      if constexpr (S > 1) __syncthreads();
+#pragma unroll
+      for (int j = 0; j < IPT; ++j)
+        if ((wave_base + j * kWave) < n) buf[rank[j]] = v[j][S - 1];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const int q = r * BLOCK + tid;
+        if (q < valid_count) v[r][S - 1] = buf[q];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int w = 0; w < S; ++w) {
+      uint32_t* buf = s_buf[0];
+      if (w > 0) __syncthreads();  // previous plane fully read
+#pragma unroll
+      for (int j = 0; j < IPT; ++j)
+        if ((wave_base + j * kWave) < n) buf[rank[j]] = v[j][w];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const int q = r * BLOCK + tid;
+        if (q < valid_count) v[r][w] = buf[q];
+      }
     }
   }
 
