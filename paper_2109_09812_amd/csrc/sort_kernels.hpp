@@ -286,7 +286,10 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   __shared__ uint32_t s_start[RADIX];
   __shared__ uint32_t s_base[RADIX];
   __shared__ __align__(16) uint32_t s_buf[NBUF][TILE];
-  __shared__ uint16_t s_dig[TILE];
+  // Key passes recompute each element's digit from its reordered words;
+  // mesh passes (whose digit needs a lookup) stage it in LDS.
+  constexpr bool kStageDigits = MODE == kPassMesh;
+  __shared__ uint16_t s_dig[kStageDigits ? TILE : 1];
   __shared__ uint32_t s_wave[WAVES];
   __shared__ uint32_t s_tile;
 
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   for (int j = 0; j < IPT; ++j) {
     if ((wave_base + j * kWave) < n) {
       rank[j] += s_start[dig[j]] + my_hist[dig[j]];
-      s_dig[rank[j]] = uint16_t(dig[j]);
+      if constexpr (kStageDigits) s_dig[rank[j]] = uint16_t(dig[j]);
     }
   }
 
@@ -531,7 +534,12 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const int q = r * BLOCK + tid;
-    opos[r] = q < valid_count ? s_base[s_dig[q]] + uint32_t(q) : 0xFFFFFFFFu;
+    uint32_t d;
+    if constexpr (kStageDigits)
+      d = s_dig[q < valid_count ? q : 0];
+    else
+      d = masked_digit<D, K>(v[r], a.lo_mask, a.hi_mask, a.shift);
+    opos[r] = q < valid_count ? s_base[d] + uint32_t(q) : 0xFFFFFFFFu;
   }
 
   // ---- scatter: consecutive q of one digit go to consecutive addresses
