@@ -234,9 +234,12 @@ def test_tet_seam_does_not_merge():
 
 
 def test_paper_quads():
-    m = meshgen.paper_quads(256)
-    got = assert_parity(m.vtx, m.idx, name="quads256")
-    assert got[0].shape[0] == 257 ** 2
+    # 256 (a power of two: the low byte of every coordinate is zero, a pass is
+    # skipped) and 300 (no such byte)
+    for q in (256, 300):
+        m = meshgen.paper_quads(q)
+        got = assert_parity(m.vtx, m.idx, name=f"quads{q}")
+        assert got[0].shape[0] == (q + 1) ** 2
 
 
 def test_cfg3_tets_full():

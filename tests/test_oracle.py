@@ -185,7 +185,7 @@ def test_cfg1_closed_form_and_invariants():
     assert (res[2] == -1).sum() == m.num_vtx - 3 * m.idx.shape[0]
 
 
-@pytest.mark.parametrize("n,expected", [(8, 81), (64, 4225)])
+@pytest.mark.parametrize("n,expected", [(7, 64), (8, 81), (64, 4225), (100, 10201)])
 def test_paper_quads_closed_form(n, expected):
     """Table 1: out = (N+1)^2 for the N x N quad generator."""
     m = meshgen.paper_quads(n)
