@@ -363,7 +363,7 @@ def bench_gather(args, torch, mrx, meshgen):
 
     def step():
         a.grad = None
-        out = GatherAttrs.apply(a, r.new2old, True)
+        out = GatherAttrs.apply(a, r.new2old, True, False)
         out.backward(wd)
 
     step()

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MRX_ABI_VERSION 2
+#define MRX_ABI_VERSION 3
 
 typedef enum {
   MRX_OK = 0,
@@ -118,8 +118,12 @@ mrx_status mrx_reindex_workspace_size(int64_t num_vtx, int32_t vtx_bytes, int64_
  *   old2new      [num_vtx] int32 (-1 = the vertex's value is not used).
  *   new2old      capacity num_vtx int32, or NULL if not wanted.
  *   out_num_vtx  device int64 scalar, receives U.
- *   dev_status   device int32 scalar receiving MRX_OK or a data error, or
- *                NULL (errors are then not reported).
+ *   dev_status   device int32 scalar, REQUIRED (NULL is
+ *                MRX_ERR_INVALID_ARGUMENT): receives MRX_OK, a data error
+ *                (MRX_ERR_INDEX_OUT_OF_RANGE) or MRX_ERR_INTERNAL (a
+ *                cross-workgroup wait gave up; all outputs invalid). The
+ *                call clears it first; read it after the stream reaches
+ *                the end of the call.
  *   workspace    device scratch of at least workspace_bytes bytes.
  *   tuning       NULL or a compiled variant.
  */
@@ -206,8 +210,12 @@ mrx_status mrx_extract_submesh(const void* vtx, int64_t num_vtx, int32_t vtx_byt
 /* Per-vertex attributes of the re-indexed mesh: out[j, c] = attrs[new2old[j], c]
  * (Section 3 notes that vertices may carry attributes).
  *   attrs     [num_old, channels] row-major, dtype 0 = fp32, 1 = fp64.
- *   new2old   [num_new] int32, each in [0, num_old) (out-of-range rows are
- *             written as zeros and reported in *dev_status when non-NULL).
+ *   new2old   [num_new] int32, each in [0, num_old). An out-of-range entry
+ *             gives a row of zeros and raises *dev_status to
+ *             MRX_ERR_INDEX_OUT_OF_RANGE (atomic max; the caller clears the
+ *             word beforehand). With dev_status NULL such entries go
+ *             unreported: pass NULL only for maps known to be in range, such
+ *             as the new2old of a successful re-index.
  *   out       [num_new, channels], same dtype. */
 mrx_status mrx_gather_attrs(const void* attrs, int64_t num_old, int32_t channels,
                             int32_t dtype, const int32_t* new2old, int64_t num_new,
@@ -217,7 +225,10 @@ mrx_status mrx_gather_attrs(const void* attrs, int64_t num_old, int32_t channels
  * grad_attrs[new2old[j], c] += grad_out[j, c].
  *   assume_injective != 0 promises that new2old has no repeated entry (true
  *   for the maps mrx_reindex_mesh produces); each row is then written with a
- *   plain store (0 + g, exact). Otherwise atomics accumulate in any order. */
+ *   plain store (0 + g, exact), and a repeated entry would lose all but one
+ *   of its contributions. With 0, atomics accumulate in any order (correct
+ *   for every map).
+ *   dev_status: as for mrx_gather_attrs. */
 mrx_status mrx_gather_attrs_backward(const void* grad_out, int64_t num_new, int32_t channels,
                                      int32_t dtype, const int32_t* new2old, int64_t num_old,
                                      void* grad_attrs, int32_t assume_injective,

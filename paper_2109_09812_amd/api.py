@@ -388,12 +388,29 @@ class GraphedBatchedReindexer(BatchedReindexer):
 _DT = {torch.float32: 0, torch.float64: 1}
 
 
+def _raise_on_status(status: torch.Tensor, where: str):
+    """One device->host read of a status word written by the library."""
+    st = int(status.cpu()[0])
+    if st == MRX_ERR_INDEX_OUT_OF_RANGE:
+        raise IndexError(f"{where}: a new2old entry is out of range")
+    check(st, where)
+
+
 class GatherAttrs(torch.autograd.Function):
     """new_attrs[j, :] = attrs[new2old[j], :] with a hand-written scatter
-    backward. new2old is a frozen int32 map (no gradient)."""
+    backward. new2old is a frozen int32 map (no gradient).
+
+    ``injective=True`` promises that new2old has no repeated entry (true for
+    the new2old of a re-index); the backward then writes each gradient row
+    with a plain store. The default (False) accumulates with atomics, which
+    is correct for every map. ``validate=True`` (default) has the forward
+    report out-of-range map entries through a device status word and raise
+    IndexError (one device->host read); with False such entries silently
+    give zero rows and dropped gradients."""
 
     @staticmethod
-    def forward(ctx, attrs: torch.Tensor, new2old: torch.Tensor, injective: bool = True):
+    def forward(ctx, attrs: torch.Tensor, new2old: torch.Tensor, injective: bool = False,
+                validate: bool = True):
         if attrs.dtype not in _DT or attrs.dim() != 2 or not attrs.is_cuda:
             raise ValueError("attrs must be a [N, C] fp32/fp64 device tensor")
         if new2old.dtype != torch.int32 or new2old.dim() != 1 or not new2old.is_cuda:
@@ -401,10 +418,13 @@ class GatherAttrs(torch.autograd.Function):
         a = attrs.contiguous()
         idx = new2old.contiguous()
         out = torch.empty((idx.numel(), a.shape[1]), dtype=a.dtype, device=a.device)
+        status = torch.zeros(1, dtype=torch.int32, device=a.device) if validate else None
         check(load().mrx_gather_attrs(_ptr(a), a.shape[0], a.shape[1], _DT[a.dtype], _ptr(idx),
-                                      idx.numel(), _ptr(out), None,
+                                      idx.numel(), _ptr(out), _ptr(status),
                                       ctypes.c_void_p(_stream_handle(a.device))),
               "mrx_gather_attrs")
+        if validate:
+            _raise_on_status(status, "mrx_gather_attrs")
         ctx.save_for_backward(idx)
         ctx.num_old = a.shape[0]
         ctx.injective = bool(injective)
@@ -415,12 +435,17 @@ class GatherAttrs(torch.autograd.Function):
         (idx,) = ctx.saved_tensors
         g = grad_out.contiguous()
         grad = torch.empty((ctx.num_old, g.shape[1]), dtype=g.dtype, device=g.device)
+        # the map is the one the forward read (and, with validate, checked)
         check(load().mrx_gather_attrs_backward(_ptr(g), g.shape[0], g.shape[1], _DT[g.dtype], _ptr(idx),
                                                ctx.num_old, _ptr(grad), int(ctx.injective), None,
                                                ctypes.c_void_p(_stream_handle(g.device))),
               "mrx_gather_attrs_backward")
-        return grad, None, None
+        return grad, None, None, None
 
 
-def gather_attrs(attrs: torch.Tensor, new2old: torch.Tensor, injective: bool = True) -> torch.Tensor:
-    return GatherAttrs.apply(attrs, new2old, injective)
+def gather_attrs(attrs: torch.Tensor, new2old: torch.Tensor, injective: bool = False,
+                 validate: bool = True) -> torch.Tensor:
+    """Differentiable attribute gather (see GatherAttrs). Pass
+    ``injective=True`` for the new2old of a re-index to get the exact
+    store-based backward."""
+    return GatherAttrs.apply(attrs, new2old, injective, validate)

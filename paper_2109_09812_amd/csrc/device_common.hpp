@@ -115,8 +115,7 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 // Control block kept in the (zeroed) workspace.
 struct Control {
   int32_t abort;        // set once any wait exceeds kSpinLimit; all waits then give up
-  int32_t status;       // internal status word used when the caller passes none
-  int32_t pad[2];
+  int32_t pad[3];
   int64_t num_groups;   // G: distinct values (per mesh, for a batch) among all vertices
   int64_t num_used;     // U of a batch (all meshes)
 };

@@ -297,7 +297,10 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   mrx_status st = validate_common(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx,
                                   old2new, workspace, workspace_bytes);
   if (st != MRX_OK) return st;
-  if (!out_num_vtx || !aligned(out_num_vtx, 8) || !aligned(new2old, 4) || !aligned(dev_status, 4))
+  // dev_status is required: it is the only channel for data errors and for
+  // a cross-workgroup wait that gave up (results invalid)
+  if (!out_num_vtx || !aligned(out_num_vtx, 8) || !aligned(new2old, 4) || !dev_status ||
+      !aligned(dev_status, 4))
     return MRX_ERR_INVALID_ARGUMENT;
   const int K = vtx_bytes / 4;
   const SortVariant* vp = pick_variant(K, tuning);
@@ -308,7 +311,7 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4;
   std::vector<Buffer> outs = {{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb},
                               {new2old, new2old ? nb : 0}, {out_num_vtx, 8},
-                              {dev_status, dev_status ? 4u : 0u}, {workspace, L.total}};
+                              {dev_status, 4u}, {workspace, L.total}};
   for (const Buffer& b : extra) outs.push_back(b);
   for (size_t i = 0; i < outs.size(); ++i)
     for (size_t j = i + 1; j < outs.size(); ++j)
@@ -350,7 +353,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
   uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
   int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
-  int32_t* status = dev_status ? dev_status : &ctl->status;
+  int32_t* status = dev_status;
 
   // per-call state: look-back words, tile counters, histograms, flags, G
   // (already cleared when a preceding step of the same call used it)
@@ -561,7 +564,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   if (st != MRX_OK) return st;
   if (num_meshes < 1 || !vtx_offsets || !elem_offsets || !out_vtx_offsets ||
       !aligned(vtx_offsets, 8) || !aligned(elem_offsets, 8) || !aligned(out_vtx_offsets, 8) ||
-      !aligned(new2old, 4) || !aligned(dev_status, 4))
+      !aligned(new2old, 4) || !dev_status || !aligned(dev_status, 4))
     return MRX_ERR_INVALID_ARGUMENT;
   const int K = vtx_bytes / 4;
   const SortVariant* vp = pick_variant(K, tuning);
@@ -573,10 +576,10 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4,
                ob = size_t(num_meshes + 1) * 8;
   if (!disjoint({{vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
-                 {out_vtx_offsets, ob}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
+                 {out_vtx_offsets, ob}, {dev_status, 4u}, {workspace, L.total},
                  {vtx_offsets, ob}, {elem_offsets, ob}, {idx == out_idx ? nullptr : idx, ib}}) ||
       !disjoint({{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb}, {new2old, new2old ? nb : 0},
-                 {out_vtx_offsets, ob}, {dev_status, dev_status ? 4u : 0u}, {workspace, L.total},
+                 {out_vtx_offsets, ob}, {dev_status, 4u}, {workspace, L.total},
                  {vtx_offsets, ob}, {elem_offsets, ob}}) ||
       (idx != out_idx && overlaps(idx, ib, out_idx, ib)))  // in place, or not at all
     return MRX_ERR_INVALID_ARGUMENT;
@@ -599,7 +602,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
   int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
-  int32_t* status = dev_status ? dev_status : &ctl->status;
+  int32_t* status = dev_status;
   const int P = L.P_key + L.P_mesh;
   int32_t* vtab = L.vtx_tab_n ? reinterpret_cast<int32_t*>(ws + L.vtx_tab) : nullptr;
   int32_t* etab = L.elem_tab_n ? reinterpret_cast<int32_t*>(ws + L.elem_tab) : nullptr;
@@ -800,7 +803,7 @@ mrx_status mrx_extract_submesh(const void* vtx, int64_t num_vtx, int32_t vtx_byt
                          ? reinterpret_cast<uint32_t*>(ws + L.counters) + L.P_key + L.P_mesh + 2
                          : nullptr;
     a.ctl = ctl;
-    a.status = dev_status ? dev_status : &ctl->status;
+    a.status = dev_status;
     a.tag = 1;
     const int64_t tiles = (num_elems + kSelectTile - 1) / kSelectTile;
     prof_mark("select_elements", s);

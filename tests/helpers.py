@@ -18,7 +18,8 @@ def check_properties(vtx, idx, out_vtx, out_idx, old2new, new2old, expected_uniq
     * out_vtx[out_idx[k]] == vtx[idx[k]] bitwise (Section 2, 'Checking our Example');
     * every output vertex is referenced;
     * new2old[j] holds out_vtx[j] and is the smallest original id with that value;
-    * old2new[i] is the new id of vtx[i]'s value, or -1 iff that value is unused.
+    * old2new[i] is the new id of vtx[i]'s value, or exactly -1 iff that
+      value is unused.
     """
     w = words(vtx)
     ow = words(out_vtx)
@@ -41,6 +42,9 @@ def check_properties(vtx, idx, out_vtx, out_idx, old2new, new2old, expected_uniq
     assert np.array_equal(w[new2old], ow)
     assert np.array_equal(old2new[new2old], np.arange(u))
     mapped = old2new >= 0
+    # the only negative value old2new may hold is -1 (value not used)
+    assert np.all(old2new[~mapped] == -1)
+    assert old2new.max(initial=-1) < u
     assert np.array_equal(w[mapped], ow[old2new[mapped]])
     # unmapped vertices hold values that are not among the outputs
     vo = _void(ow)

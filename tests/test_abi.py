@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     lib = _lib.load()
-    assert lib.mrx_abi_version() == 2
+    assert lib.mrx_abi_version() == 3
     for code, name in [(0, "MRX_OK"), (1, "MRX_ERR_INVALID_ARGUMENT"), (2, "MRX_ERR_WORKSPACE_TOO_SMALL"),
                        (3, "MRX_ERR_INDEX_OUT_OF_RANGE"), (4, "MRX_ERR_TOO_LARGE"), (5, "MRX_ERR_HIP"),
                        (6, "MRX_ERR_UNSUPPORTED"), (7, "MRX_ERR_INTERNAL")]:
@@ -117,7 +117,9 @@ def _call(**kw):
     (dict(out_idx=E), _lib.MRX_ERR_INVALID_ARGUMENT),          # out_idx == old2new
     (dict(new2old=W + 4096), _lib.MRX_ERR_INVALID_ARGUMENT),   # inside the workspace
     (dict(out_idx=B + 4), _lib.MRX_ERR_INVALID_ARGUMENT),        # overlaps idx without being it
-    (dict(tuning=(10, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
+    (dict(tuning=(7, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
+    (dict(status=None), _lib.MRX_ERR_INVALID_ARGUMENT),              # the status word is required
+    (dict(status=0x7F000102), _lib.MRX_ERR_INVALID_ARGUMENT),
     (dict(tuning=(0, 0, 0, 4)), _lib.MRX_ERR_UNSUPPORTED),          # unknown flag bit
     (dict(tuning=(8, 256, 16, 1 | 8)), _lib.MRX_ERR_UNSUPPORTED),
 ])
@@ -160,6 +162,8 @@ def test_batched_rejects_bad_arguments():
     assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
     bad = list(base); bad[11] = B + 4
     assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # out_idx overlaps idx
+    bad = list(base); bad[14] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no status word
 
 
 def test_merge_rejects_bad_arguments():
@@ -179,6 +183,8 @@ def test_merge_rejects_bad_arguments():
     assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
     bad = list(base); bad[17] = _lib.make_tuning((0, 0, 0, 4))
     assert f(*bad) == _lib.MRX_ERR_UNSUPPORTED
+    bad = list(base); bad[14] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no status word
 
 
 def test_extract_rejects_bad_arguments():
@@ -199,6 +205,8 @@ def test_extract_rejects_bad_arguments():
     assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # keep overlaps out_idx
     bad = list(base); bad[15] = 256
     assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
+    bad = list(base); bad[13] = None
+    assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no status word
 
 
 def test_gather_rejects_bad_arguments():

@@ -25,9 +25,10 @@ def _reindex(m):
     return mrx.reindex_mesh(v, i)
 
 
-@pytest.mark.parametrize("channels,dtype", [(16, torch.float32), (3, torch.float32), (16, torch.float64),
-                                            (5, torch.float64)])
-def test_forward_backward_match_cpu_autograd(channels, dtype):
+@pytest.mark.parametrize("channels,dtype,injective", [(16, torch.float32, False), (16, torch.float32, True),
+                                                      (3, torch.float32, True), (16, torch.float64, False),
+                                                      (5, torch.float64, True)])
+def test_forward_backward_match_cpu_autograd(channels, dtype, injective):
     import paper_2109_09812_amd as mrx
     m = meshgen.grid_soup(200, 0.04, 17, "g")
     r = _reindex(m)
@@ -37,9 +38,9 @@ def test_forward_backward_match_cpu_autograd(channels, dtype):
     attrs = torch.randn(m.num_vtx, channels, generator=g, dtype=dtype)
     w = torch.randn(n2o.size, channels, generator=g, dtype=dtype)
     w[0, 0] = -0.0  # a negative zero gradient must land as +0.0, as accumulation into zeros gives
-    _say("gather", channels, dtype)
+    _say("gather", channels, dtype, injective)
     a = attrs.to(DEV).requires_grad_(True)
-    out = mrx.gather_attrs(a, r.new2old)
+    out = mrx.gather_attrs(a, r.new2old, injective=injective)
     (out * w.to(DEV)).sum().backward()
     ref = oracle.gather_attrs(attrs, n2o)
     ref_grad = oracle.gather_attrs_backward(w, n2o, m.num_vtx)
@@ -65,6 +66,33 @@ def test_non_injective_backward_accumulates():
     ref = oracle.gather_attrs_backward(g, n2o.numpy(), 5)
     assert torch.allclose(a.grad.cpu(), ref, rtol=1e-12, atol=0)
     assert torch.equal(out.detach().cpu(), oracle.gather_attrs(attrs, n2o.numpy()))
+
+
+def test_default_backward_is_safe_for_repeated_entries():
+    """Without the injective promise the backward accumulates: a map with
+    repeated entries gets every contribution (integer-valued gradients make
+    each sum exact in any order)."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(12)
+    n2o = torch.from_numpy(rng.integers(0, 300, size=5000).astype(np.int32))
+    attrs = torch.randn(300, 16, generator=torch.Generator().manual_seed(12))
+    g = torch.from_numpy(rng.integers(-16, 17, size=(5000, 16)).astype(np.float32))
+    _say("default backward, repeated entries")
+    a = attrs.to(DEV).requires_grad_(True)
+    mrx.gather_attrs(a, n2o.to(DEV)).backward(g.to(DEV))
+    assert torch.equal(a.grad.cpu(), oracle.gather_attrs_backward(g, n2o.numpy(), 300))
+
+
+def test_out_of_range_map_raises():
+    import paper_2109_09812_amd as mrx
+    a = torch.zeros(10, 4, device=DEV, requires_grad=True)
+    _say("out-of-range map")
+    for bad in ([0, 10, 2], [-1, 3]):
+        with pytest.raises(IndexError):
+            mrx.gather_attrs(a, torch.tensor(bad, dtype=torch.int32, device=DEV))
+    # validate=False skips the check (documented): zero rows, no exception
+    out = mrx.gather_attrs(a, torch.tensor([1, 10], dtype=torch.int32, device=DEV), validate=False)
+    assert torch.equal(out[1].cpu(), torch.zeros(4))
 
 
 def _submesh():
