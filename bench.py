@@ -147,6 +147,27 @@ def copy_probe(torch, gib=1):
     return out
 
 
+def reference_model_bytes(n, m, g, u, r, d=8):
+    """Algorithmic bytes of the whole re-index pipeline as the plain method
+    (Section 2, Steps 1-4: stable LSD sort of (record, id) over every key bit
+    with d-bit digits, run-head flags and scan, compaction, scatter and
+    remap) must move them: N vertices of r bytes, M index entries, G
+    distinct values, U used ones. This fixed per-workload figure turns a
+    step time into the pipeline's fraction of the HBM roofline; a faster
+    algorithm that moves fewer bytes still divides this same figure."""
+    s = r + 4
+    p = -(-8 * r // d)
+    parts = {
+        "histograms": n * r,
+        "sort": n * r + n * s + (p - 1) * 2 * n * s,
+        "flag_scan": n * s + 4 * n + g * s,
+        "remap_mark": 12 * m + 2 * g,
+        "compact": g + g * s + 4 * g + u * s,
+        "final_remap": 12 * m + 12 * n,
+    }
+    return sum(parts.values()), parts
+
+
 def choose_tuning(args, vtx, idx):
     """--tuning if given, else the autotuner's pick (cached per workload shape)."""
     tuning = args.tuning
@@ -216,7 +237,16 @@ def bench_single(args, torch, mrx, meshgen):
     for name, b in model.items():
         if name in kernels and table[name][1] > 0:
             kernels[name]["model_GBps"] = round(b / (table[name][1] * 1e-3) / 1e9, 1)
+    # distinct values of the workload: every grid point plus every unused
+    # random vertex (uniform fp32 triples, distinct from each other and from
+    # the grid points)
+    g = u + (n - e * a)
+    ref_bytes, _ = reference_model_bytes(n, e * a, g, u, r_bytes)
+    pipeline = {"model": "Section 2 pipeline with 8-bit LSD digits over all key bits",
+                "model_bytes": ref_bytes, "achieved_GBps": round(ref_bytes / (ms * 1e-3) / 1e9, 1),
+                "frac": round(ref_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4), "groups": g}
     return dict(n=n, m=e * a, u=u, ms=ms, ms_prof=ms_prof, kernels=kernels, extract=extract, dist=dist, xfer=xfer,
+                pipeline=pipeline,
                 roofline_pass=dict(achieved=achieved, bytes=pass_bytes, mean_ms=passes[1]),
                 step_model_bytes_sort=step_bytes, r_bytes=r_bytes)
 
@@ -568,7 +598,11 @@ def main():
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(rp["achieved"] / PEAK_HBM_GBPS, 4) if rp["achieved"] else None,
                      "traffic": measured_traffic(), "bytes_per_launch": rp["bytes"],
-                     "mean_launch_ms": rp["mean_ms"]},
+                     "mean_launch_ms": rp["mean_ms"],
+                     # the whole step against the roofline: the plain method's
+                     # algorithmic bytes for this workload / step time / peak
+                     "pipeline_frac": single["pipeline"]["frac"],
+                     "pipeline": single["pipeline"]},
         "cpu_baseline": cpu,
         "kernels": single["kernels"],
         "ms_per_step_profiled": round(single["ms_prof"], 5),

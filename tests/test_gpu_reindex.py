@@ -254,28 +254,20 @@ def test_cfg5_soup10m_full():
     assert got[0].shape[0] == 1251 * 1281
 
 
-def test_cfg2_soup2048_properties():
+def test_cfg2_soup2048_full():
     """The 26.4M-vertex soup at full size, in the default launch
-    configuration: checked through properties that fix the result."""
+    configuration: all four outputs equal the oracle's element by element,
+    and the properties that fix the result hold."""
     m = meshgen.cfg2()
-    _say("soup2048 full size")
+    _say("soup2048 full size: GPU")
     got = gpu(m.vtx, m.idx)
+    _say("soup2048 full size: properties")
     check_properties(m.vtx, m.idx, *got, expected_unique=2048 * 2048)
-    # sampled exact check: the oracle on the sub-mesh formed by the vertices of
-    # a value-closed sample (every copy of each sampled value) gives the same
-    # relative order and representatives
-    w = words(m.vtx)
-    rng = np.random.default_rng(5)
-    pick = rng.choice(got[0].shape[0], 200, replace=False)
-    sel_vals = got[0][np.sort(pick)]
-    allv = w.view(np.dtype((np.void, 12))).reshape(-1)
-    sv = np.ascontiguousarray(sel_vals).view(np.dtype((np.void, 12))).reshape(-1)
-    members = np.nonzero(np.isin(allv, sv))[0]
-    sub_vtx = m.vtx[members]
-    sub_idx = np.arange(members.size, dtype=np.int32).reshape(-1, 1)
-    sov, _, _, sn2o = oracle.reindex(sub_vtx, sub_idx)
-    assert np.array_equal(sov, sel_vals)
-    assert np.array_equal(members[sn2o], got[3][np.sort(pick)])
+    _say("soup2048 full size: oracle (about a minute on one host core)")
+    exp = oracle.reindex(m.vtx, m.idx)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
+        assert g.shape == e.shape, (label, g.shape, e.shape)
+        assert np.array_equal(g, e), f"soup2048: {label} differs at {np.argwhere(g != e)[:5].tolist()}"
 
 
 def test_autotune_picks_a_verified_variant(tmp_path):

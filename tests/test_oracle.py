@@ -75,7 +75,7 @@ def test_worked_example_paper_steps_reproduce_printed_arrays():
 def test_worked_example_paper_tie_order_gives_printed_perm():
     vtx, idx, g = _example()
     p = g["printed"]
-    order = p["orgID_sorted_as_printed"]["value"]
+    order = p["orgID_sorted_corrected"]["value"]
     r = paper_steps.run(vtx, idx, sort_order=order)
     assert np.array_equal(r["perm"], p["perm"]["value"])
     # the printed perm is exactly the inverse of the corrected sorted orgID
