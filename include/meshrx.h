@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MRX_ABI_VERSION 3
+#define MRX_ABI_VERSION 4
 
 typedef enum {
   MRX_OK = 0,
@@ -54,8 +54,13 @@ typedef enum {
   MRX_ERR_TOO_LARGE = 4,           /* num_vtx or num_elems * arity is 2^31 or more */
   MRX_ERR_HIP = 5,                 /* a HIP launch failed */
   MRX_ERR_UNSUPPORTED = 6,         /* tuning not among the compiled variants */
-  MRX_ERR_INTERNAL = 7             /* (device) a cross-workgroup wait hit its bound; results invalid */
+  MRX_ERR_INTERNAL = 7,            /* (device) a cross-workgroup wait hit its bound; results invalid */
+  MRX_ERR_NOALLOC_TOO_LARGE = 8    /* mrx_reindex_mesh_noalloc: the call needs more workspace than
+                                      MRX_NOALLOC_SCRATCH_BYTES */
 } mrx_status;
+
+/* Size of the fixed per-GPU workspace of mrx_reindex_mesh_noalloc. */
+#define MRX_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 
 /* Kernel-shape knobs of the radix sort. All-zero shape fields mean "built-in
  * default for this record width". Only compiled combinations are accepted;
@@ -133,6 +138,33 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
                             int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status,
                             void* workspace, size_t workspace_bytes,
                             const mrx_tuning* tuning, void* stream);
+
+/* mrx_reindex_mesh without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation. Arguments, result and errors are those of
+ * mrx_reindex_mesh; the workspace is a fixed array of
+ * MRX_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends. The call allocates nothing and calls no allocating routine.
+ *
+ *   - Uses the CURRENT device's array; a non-NULL stream must belong to the
+ *     current device (else MRX_ERR_INVALID_ARGUMENT).
+ *   - The first call on a device looks up that device's array address (a
+ *     host-side query, nothing is enqueued); make that first call outside
+ *     graph capture if the capture mode forbids such queries.
+ *   - A call whose workspace (mrx_reindex_workspace_size with num_meshes == 1
+ *     and the same tuning) exceeds MRX_NOALLOC_SCRATCH_BYTES returns
+ *     MRX_ERR_NOALLOC_TOO_LARGE before enqueuing anything (12-byte records:
+ *     about a million vertices fit).
+ *   - Every call on one GPU shares that GPU's array and clears what must start
+ *     at zero itself; two calls whose executions overlap on one GPU (several
+ *     streams, several host threads) RACE and corrupt each other's results:
+ *     serialise them, e.g. on one stream.
+ */
+mrx_status mrx_reindex_mesh_noalloc(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
+                                    const int32_t* idx, int64_t num_elems, int32_t arity,
+                                    void* out_vtx, int32_t* out_idx, int32_t* old2new,
+                                    int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status,
+                                    const mrx_tuning* tuning, void* stream);
 
 /* Re-index num_meshes independent meshes packed back to back, in one launch
  * sequence (vertices of different meshes never merge, even when bitwise

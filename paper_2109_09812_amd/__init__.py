@@ -8,14 +8,14 @@ include/meshrx.h); this package only marshals arguments.
 from ._lib import MRX_TUNING_CLAIMED_TILES, MRX_TUNING_WIDE_LOOKBACK, MeshrxError, load, tunings  # noqa: F401
 
 __all__ = ["MRX_TUNING_CLAIMED_TILES", "MRX_TUNING_WIDE_LOOKBACK", "MeshrxError", "load", "tunings",
-           "reindex_mesh", "reindex_mesh_batched", "merge_meshes", "extract_submesh",
+           "reindex_mesh", "reindex_mesh_noalloc", "reindex_mesh_batched", "merge_meshes", "extract_submesh",
            "gather_attrs", "GatherAttrs", "BatchedReindexer", "GraphedBatchedReindexer",
            "Reindexer", "MeshMerger", "SubmeshExtractor", "workspace_size"]
 
 
 def __getattr__(name):
     # torch-dependent API is imported on first use
-    if name in ("reindex_mesh", "reindex_mesh_batched", "merge_meshes", "extract_submesh", "Extracted",
+    if name in ("reindex_mesh", "reindex_mesh_noalloc", "reindex_mesh_batched", "merge_meshes", "extract_submesh", "Extracted",
                 "MeshMerger", "SubmeshExtractor",
                 "gather_attrs", "GatherAttrs",
                 "BatchedReindexer", "GraphedBatchedReindexer", "workspace_size", "Reindexed", "Reindexer",

@@ -19,11 +19,13 @@ MRX_ERR_TOO_LARGE = 4
 MRX_ERR_HIP = 5
 MRX_ERR_UNSUPPORTED = 6
 MRX_ERR_INTERNAL = 7
+MRX_ERR_NOALLOC_TOO_LARGE = 8
+MRX_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 # Every symbol include/meshrx.h declares.
 EXPORTS = (
     "mrx_abi_version", "mrx_status_string", "mrx_tuning_count", "mrx_tuning_get",
-    "mrx_reindex_workspace_size", "mrx_reindex_mesh", "mrx_reindex_mesh_batched",
+    "mrx_reindex_workspace_size", "mrx_reindex_mesh", "mrx_reindex_mesh_noalloc", "mrx_reindex_mesh_batched",
     "mrx_merge_meshes", "mrx_extract_submesh",
     "mrx_gather_attrs", "mrx_gather_attrs_backward",
     "mrx_profile_enable", "mrx_profile_count", "mrx_profile_get",
@@ -57,6 +59,8 @@ _SIGS = {
                                           ctypes.POINTER(_sz)]),
     "mrx_reindex_mesh": (_i32, [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _sz, ctypes.POINTER(Tuning), _vp]),
+    "mrx_reindex_mesh_noalloc": (_i32, [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.POINTER(Tuning), _vp]),
     "mrx_reindex_mesh_batched": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(Tuning), _vp]),
     "mrx_merge_meshes": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp,

@@ -94,6 +94,27 @@ def reindex_mesh(vtx: torch.Tensor, idx: torch.Tensor, *, tuning=None, workspace
     return r.trim() if sync else r
 
 
+def reindex_mesh_noalloc(vtx: torch.Tensor, idx: torch.Tensor, out=None, *, tuning=None,
+                         sync: bool = True) -> Reindexed:
+    """``reindex_mesh`` through ``mrx_reindex_mesh_noalloc``: the library
+    works in its fixed per-GPU scratch array instead of a workspace. With
+    ``out`` (a Reindexed of capacity tensors from an earlier call, e.g. made
+    before graph capture) nothing is allocated here either."""
+    _check_vtx(vtx)
+    _check_idx(idx)
+    n, k = vtx.shape
+    dev = vtx.device
+    if out is None:
+        out = Reindexed(torch.empty_like(vtx), torch.empty_like(idx), torch.empty(n, dtype=torch.int32, device=dev),
+                        torch.empty(n, dtype=torch.int32, device=dev), torch.zeros(2, dtype=torch.int64, device=dev))
+    st = load().mrx_reindex_mesh_noalloc(
+        _ptr(vtx), n, 4 * k, _ptr(idx), idx.shape[0], idx.shape[1], _ptr(out.out_vtx), _ptr(out.out_idx),
+        _ptr(out.old2new), _ptr(out.new2old), _ptr(out.meta), ctypes.c_void_p(out.meta.data_ptr() + 8),
+        make_tuning(tuning), ctypes.c_void_p(_stream_handle(dev)))
+    check(st, "mrx_reindex_mesh_noalloc")
+    return out.trim() if sync else out
+
+
 def _offsets_ok(o: torch.Tensor) -> bool:
     return o.is_cuda and o.dtype == torch.int64 and o.dim() == 1 and o.is_contiguous()
 

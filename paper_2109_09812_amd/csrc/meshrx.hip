@@ -72,6 +72,13 @@ __global__ void k_mesh_table(const int64_t* __restrict__ off, int32_t nmesh, int
   tab[q] = int32_t(mesh_of(off, nmesh, x));
 }
 
+// Workspace of mrx_reindex_mesh_noalloc: a fixed array in the library's code
+// object, one copy per GPU the library runs on, kept until the process ends.
+// In host code this name denotes a host-side stand-in, not device memory:
+// host code only ever uses the device address that hipGetSymbolAddress
+// returns for it (scratch_of_current_device).
+static __device__ __align__(256) unsigned char scratch[MRX_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 // ---------------------------------------------------------------- profiling
@@ -446,6 +453,25 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
   return check_launch();
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (the first call on that device) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+mrx_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MRX_ERR_HIP;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MRX_ERR_HIP;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return MRX_OK;
+}
+
 }  // namespace
 }  // namespace mrx
 
@@ -465,6 +491,7 @@ const char* mrx_status_string(int32_t s) {
     case MRX_ERR_HIP: return "MRX_ERR_HIP";
     case MRX_ERR_UNSUPPORTED: return "MRX_ERR_UNSUPPORTED";
     case MRX_ERR_INTERNAL: return "MRX_ERR_INTERNAL";
+    case MRX_ERR_NOALLOC_TOO_LARGE: return "MRX_ERR_NOALLOC_TOO_LARGE";
     default: return "MRX_UNKNOWN_STATUS";
   }
 }
@@ -550,6 +577,32 @@ mrx_status mrx_reindex_mesh(const void* vtx, int64_t num_vtx, int32_t vtx_bytes,
   if (st != MRX_OK) return st;
   return launch_single(*v, L, vtx, num_vtx, vtx_bytes, idx, num_elems, arity, nullptr, out_vtx, out_idx,
                        old2new, new2old, out_num_vtx, dev_status, workspace, tuning, stream);
+}
+
+mrx_status mrx_reindex_mesh_noalloc(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, const int32_t* idx,
+                                    int64_t num_elems, int32_t arity, void* out_vtx, int32_t* out_idx,
+                                    int32_t* old2new, int32_t* new2old, int64_t* out_num_vtx,
+                                    int32_t* dev_status, const mrx_tuning* tuning, void* stream) {
+  // the stream must belong to the current device: its kernels get that
+  // device's copy of the array
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return MRX_ERR_HIP;
+  if (stream) {
+    hipDevice_t sd = -1;
+    if (hipStreamGetDevice(reinterpret_cast<hipStream_t>(stream), &sd) != hipSuccess) return MRX_ERR_HIP;
+    if (int(sd) != cur) return MRX_ERR_INVALID_ARGUMENT;
+  }
+  void* ws = nullptr;
+  mrx_status st = scratch_of_current_device(&ws);
+  if (st != MRX_OK) return st;
+  const SortVariant* v = nullptr;
+  Layout L;
+  st = validate_single(vtx, num_vtx, vtx_bytes, idx, num_elems, arity, out_vtx, out_idx, old2new, new2old,
+                       out_num_vtx, dev_status, ws, MRX_NOALLOC_SCRATCH_BYTES, tuning, {}, &v, &L);
+  if (st == MRX_ERR_WORKSPACE_TOO_SMALL) return MRX_ERR_NOALLOC_TOO_LARGE;
+  if (st != MRX_OK) return st;
+  return launch_single(*v, L, vtx, num_vtx, vtx_bytes, idx, num_elems, arity, nullptr, out_vtx, out_idx,
+                       old2new, new2old, out_num_vtx, dev_status, ws, tuning, stream);
 }
 
 mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets, int64_t total_vtx,
