@@ -34,6 +34,8 @@ EXPORTS = (
 
 MRX_TUNING_WIDE_LOOKBACK = 1
 MRX_TUNING_CLAIMED_TILES = 2
+MRX_TUNING_SORT_ALL = 4
+MRX_TUNING_HASH_GROUPS = 8
 
 
 class Tuning(ctypes.Structure):

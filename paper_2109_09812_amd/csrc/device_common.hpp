@@ -115,10 +115,58 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 // Control block kept in the (zeroed) workspace.
 struct Control {
   int32_t abort;        // set once any wait exceeds kSpinLimit; all waits then give up
-  int32_t pad[3];
+  int32_t path;         // hash grouping: 0 = groups found, 1 = a bucket did not fit, sort everything
+  int32_t pad[2];
   int64_t num_groups;   // G: distinct values (per mesh, for a batch) among all vertices
-  int64_t num_used;     // U of a batch (all meshes)
+  int64_t num_used;     // U of a batch (all meshes), or of the hash grouping
+  int64_t sort_count;   // hash grouping: elements the key sort handles (U, or N after path = 1)
 };
+
+// Which kernels of a launch sequence run, decided on the device (the host
+// never reads device data): kGateAlways, or only while Control::path is 0
+// (hash grouping succeeded) or 1 (it gave up).
+enum Gate : int32_t { kGateAlways = 0, kGateGrouped = 1, kGateSortAll = 2 };
+
+__device__ __forceinline__ bool gate_closed(int32_t gate, const Control* ctl) {
+  if (gate == kGateAlways) return false;
+  const int32_t path = __builtin_amdgcn_readfirstlane(ctl->path);
+  return gate == kGateGrouped ? path != 0 : path == 0;
+}
+
+// ---------------------------------------------------------------- record hash
+//
+// 32-bit hash of a record's K words: the block and finalisation steps of
+// MurmurHash3 (x86, 32-bit variant, by Austin Appleby). Equal records hash
+// equally; the hash grouping only needs that and a good spread of distinct
+// records over the buckets, never the order of the hashes.
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+
+template <int K, int N>
+__device__ __forceinline__ uint32_t hash_words(const uint32_t (&v)[N]) {
+  static_assert(K <= N, "record words");
+  uint32_t h = 0x21090981u;
+#pragma unroll
+  for (int w = 0; w < K; ++w) {
+    uint32_t k = v[w] * 0xcc9e2d51u;
+    k = rotl32(k, 15) * 0x1b873593u;
+    h = rotl32(h ^ k, 13) * 5u + 0xe6546b64u;
+  }
+  h ^= uint32_t(4 * K);
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t hash_ptr(const uint32_t* w) {
+  uint32_t v[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = w[i];
+  return hash_words<K>(v);
+}
 
 // The two element buffers of the LSD sort. A pass whose digit is the same
 // for every element (read off the digit histograms) would not reorder

@@ -153,7 +153,10 @@ bool wide_lookback(int64_t n, const mrx_tuning* t) {
 const SortVariant* pick_variant(int K, const mrx_tuning* t) {
   const auto& vs = variants_for(K);
   if (vs.empty()) return nullptr;
-  if (t && (t->flags & ~int32_t(MRX_TUNING_WIDE_LOOKBACK | MRX_TUNING_CLAIMED_TILES)) != 0) return nullptr;
+  constexpr int32_t known = MRX_TUNING_WIDE_LOOKBACK | MRX_TUNING_CLAIMED_TILES | MRX_TUNING_SORT_ALL |
+                             MRX_TUNING_HASH_GROUPS;
+  if (t && (t->flags & ~known) != 0) return nullptr;
+  if (t && (t->flags & MRX_TUNING_SORT_ALL) && (t->flags & MRX_TUNING_HASH_GROUPS)) return nullptr;
   if (!t || (t->digit_bits == 0 && t->block_threads == 0 && t->items_per_thread == 0)) return &vs[0];
   for (const auto& v : vs)
     if (v.D == t->digit_bits && v.block == t->block_threads && v.ipt == t->items_per_thread) return &v;
@@ -166,15 +169,33 @@ int bits_for(int64_t x) {  // bits needed to represent values 0..x
   return b;
 }
 
+// Hash grouping for a single mesh of n vertices? Its look-back words hold
+// counts below 2^30.
+constexpr int64_t kHashMinDefault = int64_t(1) << 16;
+bool use_hash_groups(int64_t n, int32_t nmesh, const mrx_tuning* t) {
+  if (nmesh != 1 || n >= kCompactLookbackLimit) return false;
+  if (t && (t->flags & MRX_TUNING_SORT_ALL)) return false;
+  if (t && (t->flags & MRX_TUNING_HASH_GROUPS)) return true;
+  return n >= kHashMinDefault;
+}
+
+// Hash passes: enough D-bit hash digits that a bucket averages at most the
+// grouping kernel's target size (1 to 3 passes).
+int hash_passes(int64_t n, const SortVariant& v) {
+  int bits = 0;
+  while ((n >> bits) > v.group_target_bucket) ++bits;
+  return std::max(1, std::min(3, (bits + v.D - 1) / v.D));
+}
+
 struct Layout {
-  int K = 0, S = 0, P_key = 0, P_mesh = 0;
-  int64_t tiles_sort = 0, tiles_scan = 0;
+  int K = 0, S = 0, P_key = 0, P_mesh = 0, P_hash = 0;  // P_hash > 0: hash grouping
+  int64_t tiles_sort = 0, tiles_scan = 0, tiles_group = 0;
   // zeroed region
   size_t ctl = 0, counters = 0, hist = 0, plan = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0,
-         used_v = 0, used_g = 0, zero_end = 0;
+         used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_lookback = 0, zero_end = 0;
   int64_t tiles_elem = 0;
   // scratch
-  size_t buf_a = 0, buf_b = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, total = 0;
+  size_t buf_a = 0, buf_b = 0, buf_c = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, total = 0;
   int64_t vtx_tab_n = 0, elem_tab_n = 0;
 };
 
@@ -184,18 +205,22 @@ constexpr int kSelectIpt = 16;
 constexpr int kSelectTile = kSelectBlock * kSelectIpt;
 
 // num_idx bounds the element count of a sub-mesh selection (arity >= 1).
-Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortVariant& v) {
+Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortVariant& v,
+                   const mrx_tuning* tuning) {
   Layout L;
   L.K = K;
   L.S = K + 1;
   L.P_key = (32 * K + v.D - 1) / v.D;
   L.P_mesh = nmesh > 1 ? (bits_for(int64_t(nmesh) - 1) + v.D - 1) / v.D : 0;
+  L.P_hash = use_hash_groups(n, nmesh, tuning) ? hash_passes(n, v) : 0;
   L.tiles_sort = (n + v.tile() - 1) / v.tile();
   L.tiles_scan = (n + kScanTile - 1) / kScanTile;
+  L.tiles_group = L.P_hash ? (n + v.group_chunk - 1) / v.group_chunk : 0;
   const int P = L.P_key + L.P_mesh;
   size_t off = 0;
   L.ctl = off;      off = align_up(off + sizeof(Control));
-  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + 3));
+  // tile counters of every look-back launch of a call (claimed tiles)
+  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + L.P_hash + 8));
   L.hist = off;     off = align_up(off + sizeof(uint32_t) * size_t(P) * size_t(v.radix()));
   L.plan = off;     off = align_up(off + sizeof(uint32_t) * size_t(2 * P + 1));  // SortBuffers::plan
   // sort look-back: tiles x radix 64-bit words, or two alternating buffers of
@@ -207,9 +232,18 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.elem_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_elem + 1));
   L.used_v = off;   off = align_up(off + size_t(n));
   L.used_g = off;   off = align_up(off + size_t(n));
+  if (L.P_hash) {
+    L.hist_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash) * size_t(v.radix()));
+    L.plan_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(2 * L.P_hash + 1));
+    L.dead_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash));
+    L.group_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_group + 1));
+  }
   L.zero_end = off;
   L.buf_a = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
+  if (L.P_hash) {
+    L.buf_c = off;  off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
+  }
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
   L.rep = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
   L.cmap = off;     off = align_up(off + sizeof(int32_t) * size_t(n));
@@ -256,12 +290,8 @@ int64_t grid_for(int64_t work, int block, int64_t cap = 8192) {
 // word): word masks select the word holding it and the next more
 // significant word.
 void set_digit(SortPassArgs& a, int K, int bit) {
-  const int lo = K - 1 - bit / 32;
-  const int hi = lo - 1;
-  for (int w = 0; w < 16; ++w) {
-    a.lo_mask[w] = (w == lo) ? 0xFFFFFFFFu : 0u;
-    a.hi_mask[w] = (w == hi) ? 0xFFFFFFFFu : 0u;
-  }
+  a.lo_word = K - 1 - bit / 32;
+  a.hi_word = a.lo_word - 1;  // -1: none
   a.shift = bit % 32;
 }
 
@@ -313,7 +343,7 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   const SortVariant* vp = pick_variant(K, tuning);
   if (!vp) return MRX_ERR_UNSUPPORTED;
   const int64_t n = num_vtx, m = num_elems * arity;
-  const Layout L = make_layout(n, m, K, 1, *vp);
+  const Layout L = make_layout(n, m, K, 1, *vp, tuning);
   if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
   const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4;
   std::vector<Buffer> outs = {{out_idx, ib}, {vtx, vb}, {out_vtx, vb}, {old2new, nb},
@@ -332,6 +362,196 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   return MRX_OK;
 }
 
+// The hash-grouping launch sequence of one mesh (see group_kernels.hpp):
+//   Step 1 (marking) with the hash-digit histograms; stable sort of
+//   (record, id | used << 31) by P_hash hash digits into X; grouping of each
+//   hash bucket in LDS (pairs (group, id) into Y, one (record, group)
+//   element per used group into C); key sort of those elements (or, if a
+//   bucket did not fit, of all N elements of X); then either the
+//   finalisation (output records, representatives, group -> new id) or, on
+//   the fallback path, Section 2's flag scan and compaction; the old2new
+//   scatter and the index remap (Step 4) are shared.
+// Buffers: A and B hold the hash passes (X = the last one written, Y = the
+// other), C the used groups; the key sort alternates between X and C.
+mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, int64_t num_vtx,
+                       int32_t vtx_bytes, const int32_t* idx, int64_t num_elems, int32_t arity,
+                       const int64_t* live_elems, void* out_vtx, int32_t* out_idx, int32_t* old2new,
+                       int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status, void* workspace,
+                       const mrx_tuning* tuning, void* stream_, bool state_zeroed) {
+  const int K = vtx_bytes / 4;
+  const int64_t n = num_vtx, m = num_elems * arity;
+  const int ph = L.P_hash;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint32_t* plan = reinterpret_cast<uint32_t*>(ws + L.plan);
+  uint32_t* hist_hash = reinterpret_cast<uint32_t*>(ws + L.hist_hash);
+  uint32_t* plan_hash = reinterpret_cast<uint32_t*>(ws + L.plan_hash);
+  uint32_t* dead_hash = reinterpret_cast<uint32_t*>(ws + L.dead_hash);
+  uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
+  uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
+  uint64_t* group_lookback = reinterpret_cast<uint64_t*>(ws + L.group_lookback);
+  const bool wide = wide_lookback(n, tuning);
+  const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
+  uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
+                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
+  uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
+  uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
+  uint32_t* buf[3] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b),
+                      reinterpret_cast<uint32_t*>(ws + L.buf_c)};
+  uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
+  int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
+  int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
+  int32_t* status = dev_status;
+  int counter = 0;  // next tile counter (claimed tiles)
+  auto next_counter = [&]() { return claimed ? counters + counter++ : nullptr; };
+
+  if (!state_zeroed) {
+    prof_mark("fill_zero", s);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
+                       static_cast<int64_t*>(nullptr));
+  }
+  // Step 1 and the hash-digit histograms
+  const MarkArgs mark{idx, m, arity, n, nullptr, nullptr, 0, nullptr, live_elems, used_v, status};
+  prof_mark(m > 0 ? "mark_histogram" : "histogram", s);
+  v.hash_hist(m > 0 ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
+  if (n > 0) {
+    // stable sort by the hash digits; every hash pass runs (dead flags go to
+    // a word nobody reads), so the elements end in X = buf[(ph - 1) & 1]
+    prof_mark("scan_buckets", s);
+    v.scan(hist_hash, ph, n, nullptr, dead_hash, s);
+    const SortBuffers sbh{{buf[0], buf[1]}, plan_hash, ph};
+    int gp = 0;  // index of the pass in the call (look-back buffer parity, tag)
+    for (int p = 0; p < ph; ++p, ++gp) {
+      SortPassArgs a{};
+      a.vtx = static_cast<const uint32_t*>(vtx);
+      a.bufs = sbh;
+      a.pass = p;
+      a.used = used_v;
+      a.bucket_base = hist_hash + size_t(p) * v.radix();
+      a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[gp & 1]);
+      a.lookback_next = lb32[(gp + 1) & 1];
+      a.tile_counter = next_counter();
+      a.ctl = ctl;
+      a.status = status;
+      a.n = n;
+      a.lo_word = a.hi_word = -1;
+      a.shift = p * v.D;
+      a.tag = uint32_t(gp + 1);
+      prof_mark(p == 0 ? "onesweep_hash_first" : "onesweep_hash", s);
+      v.pass(a, p == 0 ? kPassFirstHash : kPassHash, wide, L.tiles_sort, s);
+    }
+    uint32_t* X = buf[(ph - 1) & 1];
+    uint32_t* Y = buf[((ph - 1) & 1) ^ 1];
+    uint2* pairs = reinterpret_cast<uint2*>(Y);
+
+    // group each hash bucket
+    GroupArgs g{};
+    g.elems = X;
+    g.n = n;
+    g.bucket_mask = ph * v.D >= 32 ? 0xFFFFFFFFu : (1u << (ph * v.D)) - 1u;
+    g.pairs = pairs;
+    g.rep = rep;
+    g.cmap = cmap;
+    g.uelems = buf[2];
+    g.lookback = group_lookback;
+    g.tile_counter = next_counter();
+    g.ctl = ctl;
+    g.status = status;
+    prof_mark("group", s);
+    v.group(g, L.tiles_group, s);
+
+    // key sort: the used groups from C (or, on the fallback path, all of X)
+    const SortBuffers sbk{{X, buf[2]}, plan, L.P_key};
+    const HistArgs ha{{buf[2], X}, &ctl->path, n, &ctl->sort_count, hist};
+    prof_mark("histogram", s);
+    v.elem_hist(ha, s);
+    prof_mark("scan_buckets", s);
+    v.scan(hist, L.P_key, n, &ctl->sort_count, plan + L.P_key + 1, s);
+    prof_mark("sort_plan", s);
+    hipLaunchKernelGGL(k_group_sort_plan, dim3(1), dim3(64), 0, s, sbk, static_cast<const Control*>(ctl));
+    for (int p = 0; p < L.P_key; ++p, ++gp) {
+      SortPassArgs a{};
+      a.bufs = sbk;
+      a.pass = p;
+      a.bucket_base = hist + size_t(p) * v.radix();
+      a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[gp & 1]);
+      a.lookback_next = lb32[(gp + 1) & 1];
+      a.tile_counter = next_counter();
+      a.ctl = ctl;
+      a.status = status;
+      a.n = n;
+      a.n_dev = &ctl->sort_count;
+      set_digit(a, K, p * v.D);
+      a.tag = uint32_t(gp + 1);
+      prof_mark("onesweep", s);
+      v.pass(a, kPassKey, wide, L.tiles_sort, s);
+    }
+    // grouping path: sorted position = new id
+    FinalizeArgs fa{};
+    fa.bufs = sbk;
+    fa.rep = rep;
+    fa.cmap = cmap;
+    fa.out_vtx = static_cast<uint32_t*>(out_vtx);
+    fa.new2old = new2old;
+    fa.out_num = out_num_vtx;
+    fa.cap = n;
+    fa.ctl = ctl;
+    fa.status = status;
+    prof_mark("finalize", s);
+    v.finalize(fa, grid_for(n, 256, 4096), s);
+    // fallback path: Section 2's flags, scans and compaction over all of X
+    FlagScanArgs f{};
+    f.bufs = sbk;
+    f.n = n;
+    f.uniq = uniq;
+    f.rep = rep;
+    f.used_g = used_g;
+    f.lookback = scan_lookback;
+    f.tile_counter = next_counter();
+    f.ctl = ctl;
+    f.status = status;
+    f.tag = uint32_t(gp + 1);
+    f.pairs = pairs;
+    f.gate = kGateSortAll;
+    prof_mark("flag_scan", s);
+    v.flag_scan(f, false, L.tiles_scan, s);
+    CompactArgs c{};
+    c.used_g = used_g;
+    c.uniq = uniq;
+    c.rep = rep;
+    c.K = K;
+    c.out_vtx = static_cast<uint32_t*>(out_vtx);
+    c.new2old = new2old;
+    c.cmap = cmap;
+    c.out_num = out_num_vtx;
+    c.cap = n;
+    c.lookback = scan_lookback;
+    c.tile_counter = next_counter();
+    c.ctl = ctl;
+    c.status = status;
+    c.tag = uint32_t(gp + 2);
+    c.gate = kGateSortAll;
+    prof_mark("compact", s);
+    hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
+    // both paths: Step 4's map
+    prof_mark("old2new", s);
+    hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
+                       sbk, static_cast<const uint2*>(pairs), cmap, n, nullptr, nullptr, 0, nullptr, old2new);
+  }
+  // Step 4: remap the index array
+  if (m > 0) {
+    prof_mark("remap", s);
+    hipLaunchKernelGGL((k_remap<false>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, idx, m, arity, n,
+                       nullptr, nullptr, 0, nullptr, live_elems, old2new, out_idx);
+  }
+  prof_mark(nullptr, s);
+  return check_launch();
+}
+
 // The single-mesh launch sequence (Section 2, Steps 1-4). live_elems
 // (device, nullable) limits the index array to its first *live_elems
 // elements; num_elems is then only a capacity.
@@ -340,6 +560,9 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
                          const int64_t* live_elems, void* out_vtx, int32_t* out_idx, int32_t* old2new,
                          int32_t* new2old, int64_t* out_num_vtx, int32_t* dev_status, void* workspace,
                          const mrx_tuning* tuning, void* stream_, bool state_zeroed = false) {
+  if (L.P_hash)
+    return launch_hash(v, L, vtx, num_vtx, vtx_bytes, idx, num_elems, arity, live_elems, out_vtx, out_idx,
+                       old2new, new2old, out_num_vtx, dev_status, workspace, tuning, stream_, state_zeroed);
   const int K = vtx_bytes / 4;
   const int64_t n = num_vtx, m = num_elems * arity;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
@@ -388,7 +611,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
       v.hist(static_cast<const uint32_t*>(vtx), n, hist, s);
     }
     prof_mark("scan_buckets", s);
-    v.scan(hist, L.P_key, n, plan + L.P_key + 1, s);
+    v.scan(hist, L.P_key, n, nullptr, plan + L.P_key + 1, s);
     const SortBuffers sb{{buf[0], buf[1]}, plan, L.P_key};
     for (int p = 0; p < L.P_key; ++p) {
       SortPassArgs a{};
@@ -398,6 +621,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
       a.used = used_v;
       a.bucket_base = hist + size_t(p) * v.radix();
       a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
+      a.lookback_next = lb32[(p + 1) & 1];
       a.tile_counter = claimed ? counters + p : nullptr;
       a.ctl = ctl;
       a.status = status;
@@ -441,7 +665,7 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       sb, cmap, n, nullptr, nullptr, 0, nullptr, old2new);
+                       sb, static_cast<const uint2*>(nullptr), cmap, n, nullptr, nullptr, 0, nullptr, old2new);
   }
   // Step 4: remap the index array
   if (m > 0) {
@@ -559,7 +783,7 @@ mrx_status mrx_reindex_workspace_size(int64_t num_vtx, int32_t vtx_bytes, int64_
   if (num_vtx > kMaxCount || num_idx > kMaxCount) return MRX_ERR_TOO_LARGE;
   const SortVariant* v = pick_variant(vtx_bytes / 4, tuning);
   if (!v) return MRX_ERR_UNSUPPORTED;
-  *bytes = make_layout(num_vtx, num_idx, vtx_bytes / 4, num_meshes, *v).total;
+  *bytes = make_layout(num_vtx, num_idx, vtx_bytes / 4, num_meshes, *v, tuning).total;
   return MRX_OK;
 }
 
@@ -624,7 +848,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
   if (!vp) return MRX_ERR_UNSUPPORTED;
   const SortVariant& v = *vp;
   const int64_t n = total_vtx, m = total_elems * arity;
-  const Layout L = make_layout(n, m, K, num_meshes, v);
+  const Layout L = make_layout(n, m, K, num_meshes, v, tuning);
   if (workspace_bytes < L.total) return MRX_ERR_WORKSPACE_TOO_SMALL;
   const size_t vb = size_t(n) * vtx_bytes, ib = size_t(m) * 4, nb = size_t(n) * 4,
                ob = size_t(num_meshes + 1) * 8;
@@ -696,7 +920,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     prof_mark("mesh_histogram", s);
     v.mesh_hist(vtx_offsets, num_meshes, L.P_mesh, hist + size_t(L.P_key) * v.radix(), s);
     prof_mark("scan_buckets", s);
-    v.scan(hist, P, n, plan + P + 1, s);
+    v.scan(hist, P, n, nullptr, plan + P + 1, s);
     const SortBuffers sb{{buf[0], buf[1]}, plan, P};
     for (int p = 0; p < P; ++p) {
       SortPassArgs a{};
@@ -706,6 +930,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
       a.used = used_v;
       a.bucket_base = hist + size_t(p) * v.radix();
       a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[p & 1]);
+      a.lookback_next = lb32[(p + 1) & 1];
       a.tile_counter = claimed ? counters + p : nullptr;
       a.ctl = ctl;
       a.status = status;
@@ -764,7 +989,7 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
                        static_cast<const int64_t*>(&ctl->num_used), n, out_vtx_offsets);
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<true>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
-                       sb, cmap, n, vtx_offsets, out_vtx_offsets, num_meshes,
+                       sb, static_cast<const uint2*>(nullptr), cmap, n, vtx_offsets, out_vtx_offsets, num_meshes,
                        static_cast<const int32_t*>(vtab), old2new);
     if (new2old) {
       prof_mark("localize_new2old", s);
@@ -853,7 +1078,7 @@ mrx_status mrx_extract_submesh(const void* vtx, int64_t num_vtx, int32_t vtx_byt
     a.out_count = out_num_elems;
     a.lookback = reinterpret_cast<uint64_t*>(ws + L.elem_lookback);
     a.tile_counter = (tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES))
-                         ? reinterpret_cast<uint32_t*>(ws + L.counters) + L.P_key + L.P_mesh + 2
+                         ? reinterpret_cast<uint32_t*>(ws + L.counters) + L.P_key + L.P_mesh + L.P_hash + 7
                          : nullptr;
     a.ctl = ctl;
     a.status = dev_status;

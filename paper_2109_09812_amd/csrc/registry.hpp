@@ -6,6 +6,7 @@
 
 #include <vector>
 
+#include "group_kernels.hpp"
 #include "scan_kernels.hpp"
 #include "sort_kernels.hpp"
 
@@ -16,28 +17,29 @@ constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 16;
 constexpr int kScanTile = kScanBlock * kScanIpt;
 
-// Step 1 and the key-pass digit histograms of Step 2 as one launch. The two
-// read different arrays and are held up by different units (scattered byte
+// Step 1 and the digit histograms of Step 2 as one launch. The two read
+// different arrays and are held up by different units (scattered byte
 // stores for the marking, LDS atomics for the histograms), so their tiles are
 // spread evenly over one grid and run side by side. With H histogram tiles
 // and M marking tiles, h(b) = floor(b * H / (H + M)) counts the histogram
 // tiles before block b: block b is histogram tile h(b) if h(b + 1) > h(b),
-// else marking tile b - h(b).
-template <int K, int D, int BLOCK, int GROUPS, bool BATCHED>
+// else marking tile b - h(b). DG chooses the digits: every key pass of the
+// LSD sort, or the hash passes of the hash grouping.
+template <class DG, int K, int D, int BLOCK, int GROUPS, bool BATCHED>
 __global__ __launch_bounds__(BLOCK) void k_mark_histogram(MarkArgs ma, const uint32_t* __restrict__ vtx,
                                                           int64_t n, uint32_t* __restrict__ hist,
                                                           int64_t hist_tiles, int64_t mark_tiles) {
   static_assert(BLOCK == kRandBlock, "both halves use the marking block shape");
-  constexpr int P = (32 * K + D - 1) / D;
-  __shared__ uint32_t s_h[P << D];
+  constexpr int WORDS = DG::kPasses << D;
+  __shared__ uint32_t s_h[WORDS];
   const int64_t total = hist_tiles + mark_tiles;
   const int64_t b = blockIdx.x;
   const int64_t h0 = b * hist_tiles / total;
   const int64_t h1 = (b + 1) * hist_tiles / total;
   if (h1 > h0) {
-    for (int i = threadIdx.x; i < (P << D); i += BLOCK) s_h[i] = 0;
-    __syncthreads();
-    histogram_chunk<K, D, BLOCK, GROUPS>(vtx, n, hist, s_h, h0);
+    zero_histograms<WORDS, BLOCK>(s_h);
+    histogram_chunk<DG, K, D, K, BLOCK, GROUPS>(vtx, n, s_h, h0);
+    flush_histograms<WORDS, BLOCK>(s_h, hist);
   } else {
     mark_used_tile<BATCHED>(ma, b - h0);
   }
@@ -60,10 +62,22 @@ struct SortVariant {
   void (*mesh_hist)(const int64_t* off, int32_t nmesh, int32_t passes, uint32_t* hist,
                     hipStream_t) = nullptr;
   // per-pass exclusive scan of the histograms, and the passes whose digit
-  // is the same for all n elements (dead[p] = 1)
-  void (*scan)(uint32_t* hist, int32_t passes, int64_t n, uint32_t* dead, hipStream_t) = nullptr;
+  // is the same for all min(n, *n_dev) elements (dead[p] = 1)
+  void (*scan)(uint32_t* hist, int32_t passes, int64_t n, const int64_t* n_dev, uint32_t* dead,
+               hipStream_t) = nullptr;
   // run-head flags + prefix sum + scatters over the sorted elements
   void (*flag_scan)(const FlagScanArgs&, bool batched, int64_t grid, hipStream_t) = nullptr;
+  // hash grouping: key-digit histograms of sort elements (buffer and count
+  // read on the device), hash-digit histograms of the records for `ph`
+  // passes (with Step 1's marking when `mark` is given), the grouping kernel
+  // and the finalisation after the key sort of the used groups
+  void (*elem_hist)(const HistArgs&, hipStream_t) = nullptr;
+  void (*hash_hist)(const MarkArgs* mark, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
+                    hipStream_t) = nullptr;
+  void (*group)(const GroupArgs&, int64_t grid, hipStream_t) = nullptr;
+  void (*finalize)(const FinalizeArgs&, int64_t grid, hipStream_t) = nullptr;
+  int group_chunk = 0;           // sorted positions per grouping workgroup
+  int group_target_bucket = 0;   // average bucket size the hash passes aim for
 
   int tile() const { return block * ipt; }
   int radix() const { return 1 << D; }

@@ -90,6 +90,8 @@ struct FlagScanArgs {
   const int32_t* mesh_tab; // batched: bucket table of mesh_off (mesh_of)
   int32_t nmesh;
   uint32_t tag;
+  uint2* pairs;            // nullable: receives the pairs instead of bufs.spare()
+  int32_t gate;            // Gate: run always, or only on one path of the hash grouping
 };
 
 template <int K, int BLOCK, int IPT, bool BATCHED>
@@ -102,12 +104,13 @@ __global__ __launch_bounds__(BLOCK) void k_flag_scan(FlagScanArgs a) {
   __shared__ uint32_t s_prefix;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  if (gate_closed(a.gate, a.ctl)) return;  // the same for every workgroup
   const uint32_t fin = a.bufs.entry(a.bufs.passes);  // requested before the barrier
   const uint32_t tile = claim_tile(a.tile_counter, &s_tile);
   const int64_t n = a.n;
   const int64_t wave_base = int64_t(tile) * TILE + int64_t(wave) * (kWave * IPT) + lane;
   const uint32_t* sorted = a.bufs.buf[fin & 1u];
-  uint2* pairs = reinterpret_cast<uint2*>(a.bufs.buf[(fin & 1u) ^ 1u]);
+  uint2* pairs = a.pairs ? a.pairs : reinterpret_cast<uint2*>(a.bufs.buf[(fin & 1u) ^ 1u]);
 
   uint32_t id[IPT];
   uint32_t incl[IPT];   // heads at or before this element within the wave's (j, lane) order
@@ -225,6 +228,7 @@ struct CompactArgs {
   Control* ctl;
   int32_t* status;
   uint32_t tag;
+  int32_t gate;            // Gate: run always, or only on one path of the hash grouping
 };
 
 template <int BLOCK, int IPT>
@@ -236,6 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
   __shared__ uint32_t s_prefix;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  if (gate_closed(a.gate, a.ctl)) return;  // the same for every workgroup
   const uint32_t tile = claim_tile(a.tile_counter, &s_tile);
   const int64_t G = a.ctl->num_groups;
   if (int64_t(tile) * TILE >= G) return;  // whole block: tile is uniform
@@ -296,18 +301,19 @@ __global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
 
 // Step 4's map: old2new[org] = new id of the group of each sorted element
 // (-1 if the group is unused), a scatter from the (group id, original id)
-// pairs that the flag scan left in the spare sort buffer; the cmap reads
-// follow the non-decreasing group ids. For a batch the new id is made
-// mesh-local with the mesh's output offset.
+// pairs that the flag scan left in the spare sort buffer (or that the hash
+// grouping left in `pairs_in`); the cmap reads follow the non-decreasing
+// group ids. For a batch the new id is made mesh-local with the mesh's
+// output offset.
 template <bool BATCHED>
-__global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(SortBuffers bufs,
+__global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(SortBuffers bufs, const uint2* pairs_in,
                                                                 const int32_t* __restrict__ cmap, int64_t n,
                                                                 const int64_t* __restrict__ vtx_off,
                                                                 const int64_t* __restrict__ out_off,
                                                                 int32_t nmesh, const int32_t* __restrict__ vtx_tab,
                                                                 int32_t* __restrict__ old2new) {
   constexpr int TILE = kRandBlock * kScatterItems;
-  const uint2* __restrict__ pairs = reinterpret_cast<const uint2*>(bufs.spare());
+  const uint2* __restrict__ pairs = pairs_in ? pairs_in : reinterpret_cast<const uint2*>(bufs.spare());
   __shared__ int32_t s_cmap[TILE];
   __shared__ uint32_t s_g[2];
   const int64_t t0 = int64_t(blockIdx.x) * TILE;

@@ -2,6 +2,7 @@
 // Built once per K with -DMRX_INST_K=<K>.
 #include <algorithm>
 
+#include "group_kernels.hpp"
 #include "registry.hpp"
 
 #ifndef MRX_INST_K
@@ -25,6 +26,12 @@ void launch_pass_w(const SortPassArgs& a, int mode, int64_t grid, hipStream_t s)
     case kPassKey:
       hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassKey, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
+    case kPassFirstHash:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassFirstHash, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
+      break;
+    case kPassHash:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassHash, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
+      break;
     default:
       hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassMesh, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
@@ -47,10 +54,60 @@ constexpr int kHistGroups = 4;
 template <int D>
 void launch_hist(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) {
   constexpr int B = 256, GROUPS = kHistGroups;
-  constexpr int R = 4 / gcd4(K);
+  constexpr int R = items_per_group(K);
   const int64_t per_block = int64_t(B) * GROUPS * R;
   const int64_t grid = (n + per_block - 1) / per_block;
-  if (grid > 0) hipLaunchKernelGGL((k_histogram<K, D, B, GROUPS>), dim3(grid), dim3(B), 0, s, vtx, n, hist);
+  const HistArgs a{{vtx, vtx}, nullptr, n, nullptr, hist};
+  if (grid > 0)
+    hipLaunchKernelGGL((k_histogram<KeyDigits<K, D>, K, D, K, B, GROUPS>), dim3(grid), dim3(B), 0, s, a);
+}
+
+// Key-digit histograms of sort elements (K + 1 words) whose buffer and count
+// are read on the device; the grid covers a.n (the capacity).
+template <int D>
+void launch_elem_hist(const HistArgs& a, hipStream_t s) {
+  constexpr int B = 256, GROUPS = kHistGroups;
+  constexpr int R = items_per_group(K + 1);
+  const int64_t per_block = int64_t(B) * GROUPS * R;
+  const int64_t grid = (a.n + per_block - 1) / per_block;
+  if (grid > 0)
+    hipLaunchKernelGGL((k_histogram<KeyDigits<K, D>, K, D, K + 1, B, GROUPS>), dim3(grid), dim3(B), 0, s, a);
+}
+
+// Hash-digit histograms of the records for ph passes, with Step 1's marking
+// in the same launch when there is something to mark.
+template <int D, int PH>
+void launch_hash_hist_ph(const MarkArgs* ma, const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) {
+  constexpr int B = kRandBlock, GROUPS = kHistGroups;
+  constexpr int R = items_per_group(K);
+  const int64_t per_block = int64_t(B) * GROUPS * R;
+  const int64_t ht = (n + per_block - 1) / per_block;
+  if (ma && ma->m > 0) {
+    const int64_t mt = (ma->m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
+    hipLaunchKernelGGL((k_mark_histogram<HashDigits<K, D, PH>, K, D, B, GROUPS, false>), dim3(ht + mt), dim3(B),
+                       0, s, *ma, vtx, n, hist, ht, mt);
+  } else if (ht > 0) {
+    const HistArgs a{{vtx, vtx}, nullptr, n, nullptr, hist};
+    hipLaunchKernelGGL((k_histogram<HashDigits<K, D, PH>, K, D, K, B, GROUPS>), dim3(ht), dim3(B), 0, s, a);
+  }
+}
+
+template <int D>
+void launch_hash_hist(const MarkArgs* ma, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
+                      hipStream_t s) {
+  switch (ph) {
+    case 1: launch_hash_hist_ph<D, 1>(ma, vtx, n, hist, s); break;
+    case 2: launch_hash_hist_ph<D, 2>(ma, vtx, n, hist, s); break;
+    default: launch_hash_hist_ph<D, 3>(ma, vtx, n, hist, s); break;
+  }
+}
+
+void launch_group(const GroupArgs& a, int64_t grid, hipStream_t s) {
+  if (grid > 0) hipLaunchKernelGGL((k_group<K>), dim3(grid), dim3(GroupShape<K>::BLOCK), 0, s, a);
+}
+
+void launch_finalize(const FinalizeArgs& a, int64_t grid, hipStream_t s) {
+  if (grid > 0) hipLaunchKernelGGL((k_group_finalize<K>), dim3(grid), dim3(256), 0, s, a);
 }
 
 // Every block of the fused launch holds the histogram's LDS; beyond this size
@@ -61,7 +118,7 @@ template <int D>
 bool mark_hist_applies(int64_t n, int64_t m) {
   constexpr int P = (32 * K + D - 1) / D;
   if (P * (1 << D) * 4 > kFusedHistLds || n <= 0 || m <= 0) return false;
-  constexpr int64_t per_block = int64_t(kRandBlock) * kHistGroups * (4 / gcd4(K));
+  constexpr int64_t per_block = int64_t(kRandBlock) * kHistGroups * items_per_group(K);
   const int64_t ht = (n + per_block - 1) / per_block;
   const int64_t mt = (m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
   return ht + mt <= INT32_MAX;
@@ -74,16 +131,16 @@ void launch_mark_hist(const MarkArgs& ma, bool batched, const uint32_t* vtx, int
   constexpr int P = (32 * K + D - 1) / D;
   if constexpr (P * (1 << D) * 4 <= kFusedHistLds) {
     if (!mark_hist_applies<D>(n, ma.m)) return;
-    constexpr int R = 4 / gcd4(K);
+    constexpr int R = items_per_group(K);
     const int64_t per_block = int64_t(B) * GROUPS * R;
     const int64_t ht = (n + per_block - 1) / per_block;
     const int64_t mt = (ma.m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
     if (batched)
-      hipLaunchKernelGGL((k_mark_histogram<K, D, B, GROUPS, true>), dim3(ht + mt), dim3(B), 0, s, ma, vtx, n,
-                         hist, ht, mt);
+      hipLaunchKernelGGL((k_mark_histogram<KeyDigits<K, D>, K, D, B, GROUPS, true>), dim3(ht + mt), dim3(B), 0, s,
+                         ma, vtx, n, hist, ht, mt);
     else
-      hipLaunchKernelGGL((k_mark_histogram<K, D, B, GROUPS, false>), dim3(ht + mt), dim3(B), 0, s, ma, vtx, n,
-                         hist, ht, mt);
+      hipLaunchKernelGGL((k_mark_histogram<KeyDigits<K, D>, K, D, B, GROUPS, false>), dim3(ht + mt), dim3(B), 0,
+                         s, ma, vtx, n, hist, ht, mt);
   }
 }
 
@@ -95,8 +152,10 @@ void launch_mesh_hist(const int64_t* off, int32_t nmesh, int32_t passes, uint32_
 }
 
 template <int D>
-void launch_scan(uint32_t* hist, int32_t passes, int64_t n, uint32_t* dead, hipStream_t s) {
-  if (passes > 0) hipLaunchKernelGGL((k_scan_buckets<D, 256>), dim3(passes), dim3(256), 0, s, hist, n, dead);
+void launch_scan(uint32_t* hist, int32_t passes, int64_t n, const int64_t* n_dev, uint32_t* dead,
+                 hipStream_t s) {
+  if (passes > 0)
+    hipLaunchKernelGGL((k_scan_buckets<D, 256>), dim3(passes), dim3(256), 0, s, hist, n, n_dev, dead);
 }
 
 void launch_flag_scan(const FlagScanArgs& a, bool batched, int64_t grid, hipStream_t s) {
@@ -121,6 +180,12 @@ SortVariant make() {
   v.mesh_hist = &launch_mesh_hist<D>;
   v.scan = &launch_scan<D>;
   v.flag_scan = &launch_flag_scan;
+  v.elem_hist = &launch_elem_hist<D>;
+  v.hash_hist = &launch_hash_hist<D>;
+  v.group = &launch_group;
+  v.finalize = &launch_finalize;
+  v.group_chunk = GroupShape<K>::CHUNK;
+  v.group_target_bucket = GroupShape<K>::TARGET_BUCKET;
   return v;
 }
 

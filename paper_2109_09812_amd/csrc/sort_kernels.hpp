@@ -14,45 +14,45 @@
 
 namespace mrx {
 
-enum PassMode : int { kPassFirst = 0, kPassKey = 1, kPassMesh = 2 };
+enum PassMode : int {
+  kPassFirst = 0,      // reads the caller's records (+ referenced flags), digit from the key words
+  kPassKey = 1,        // element to element, digit from the key words
+  kPassMesh = 2,       // element to element, digit from the element's mesh id (batches)
+  kPassFirstHash = 3,  // as kPassFirst, digit from the record's hash (hash grouping)
+  kPassHash = 4,       // as kPassKey, digit from the record's hash
+};
 
 struct SortPassArgs {
-  const uint32_t* vtx;          // first pass: vertex records (K words)
+  const uint32_t* vtx;          // first passes: vertex records (K words)
   SortBuffers bufs;             // elements (K+1 words); the first pass writes buf[0] and the plan
-  const uint8_t* used;          // first pass: 1 if some index entry references the vertex
+  const uint8_t* used;          // first passes: 1 if some index entry references the vertex (nullable)
   const uint32_t* bucket_base;  // [RADIX] start of each digit's bucket in the output
   // Look-back words, [tiles][RADIX]: LbTagged words (wide launches), or
-  // LbCompact words. These alternate between two buffers of tiles * RADIX
-  // words, the second right after the first (pass p uses buffer p % 2); each
-  // launch clears its rows of the buffer the next pass uses.
+  // LbCompact words. Compact words alternate between two buffers of
+  // tiles * RADIX words: each launch clears its rows of `lookback_next`,
+  // the buffer the next pass uses.
   void* lookback;
+  void* lookback_next;
   uint32_t* tile_counter;
   Control* ctl;
   int32_t* status;
   const int64_t* mesh_off;      // mesh passes: [nmesh+1] vertex offsets
   const int32_t* mesh_tab;      // mesh passes: bucket table of mesh_off (mesh_of)
+  const int64_t* n_dev;         // non-null: the element count is min(n, *n_dev), read on the device
   int32_t nmesh;
-  // The digit is bits [shift, shift + D) of (word_hi:word_lo). The words are
-  // selected with per-word masks (all-ones for the chosen word, zero for the
-  // others) rather than an index, so element words stay in registers.
-  uint32_t lo_mask[16];
-  uint32_t hi_mask[16];
-  int32_t shift;                // bit offset of the digit inside word_lo (mesh passes: inside the mesh id)
+  // Key passes: the digit is bits [shift, shift + D) of (w[hi_word]:w[lo_word])
+  // (hi_word < 0: none). Hash passes: bits [shift, shift + D) of the hash;
+  // mesh passes: of the mesh id.
+  int32_t lo_word, hi_word;
+  int32_t shift;
   int64_t n;
   uint32_t tag;
-  int32_t pass;                 // index of this pass
+  int32_t pass;                 // index of this pass in the plan
 };
 // Kept within 256 bytes: a larger argument block measurably raised the
 // register count of the pass kernels on gfx950 (e.g. 125 -> 138 VGPRs for
 // 512 x 16 tiles, one wave fewer per SIMD).
 static_assert(sizeof(SortPassArgs) <= 256, "pass arguments outgrew 256 bytes");
-
-// LbCompact buffer of the pass after `pass`: the other half of the pair
-// (tiles = the grid size).
-__device__ __forceinline__ uint32_t* lookback_next_of(void* lookback, int32_t pass, int64_t tiles, int radix) {
-  uint32_t* lb = static_cast<uint32_t*>(lookback);
-  return (pass & 1) ? lb - tiles * radix : lb + tiles * radix;
-}
 
 // (word_hi:word_lo) >> shift, masked to D bits, with the words chosen by masks.
 template <int D, int K, int N>
@@ -81,128 +81,155 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int shift
 }
 
 // ----------------------------------------------------------------------------
-// Digit histograms of every key pass in one read of the records.
-// hist[p * RADIX + b] += number of records whose pass-p digit is b.
+// Digit histograms of every pass in one read of the items.
+// hist[p * RADIX + b] += number of items whose pass-p digit is b.
 //
-// Records are read in groups of R = 4 / gcd(K, 4) consecutive records, i.e.
-// R*K words = a whole number of 16-byte vectors, so a wave reads one
-// contiguous stretch per load instruction (when the records are 16-byte
-// aligned; otherwise word by word).
+// Item i's key words are src[i * STRIDE .. i * STRIDE + K): caller records
+// (STRIDE = K) or sort elements (STRIDE = K + 1). Items are read in groups
+// of R = 4 / gcd(STRIDE, 4) consecutive ones, i.e. R*STRIDE words = a whole
+// number of 16-byte vectors, so a wave reads one contiguous stretch per load
+// instruction (when src is 16-byte aligned; otherwise word by word).
 constexpr int gcd4(int k) { return (k % 4 == 0) ? 4 : (k % 2 == 0) ? 2 : 1; }
 
+// Digits of every LSD key pass of a K-word record.
 template <int K, int D>
-__device__ __forceinline__ void hist_record(const uint32_t* w, uint32_t* s_h, uint32_t* last,
-                                            uint32_t* run) {
-  constexpr int RADIX = 1 << D;
-  constexpr int P = (32 * K + D - 1) / D;
+struct KeyDigits {
+  static constexpr int kPasses = (32 * K + D - 1) / D;
+  static __device__ __forceinline__ void digits(const uint32_t* w, uint32_t (&d)[kPasses]) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int bit = p * D;
-    const int wi = K - 1 - bit / 32;
-    const int hi = wi - 1;
-    const uint32_t d = digit_of<D>(w[wi], hi >= 0 ? w[hi >= 0 ? hi : 0] : 0u, bit % 32);
-    if (run[p] != 0 && d == last[p]) {
+    for (int p = 0; p < kPasses; ++p) {
+      const int bit = p * D;
+      const int wi = K - 1 - bit / 32;
+      const int hi = wi - 1;
+      d[p] = digit_of<D>(w[wi], hi >= 0 ? w[hi >= 0 ? hi : 0] : 0u, bit % 32);
+    }
+  }
+};
+
+// Digits of the PH hash passes of a K-word record (hash grouping).
+template <int K, int D, int PH>
+struct HashDigits {
+  static constexpr int kPasses = PH;
+  static __device__ __forceinline__ void digits(const uint32_t* w, uint32_t (&d)[kPasses]) {
+    const uint32_t h = hash_ptr<K>(w);
+#pragma unroll
+    for (int p = 0; p < PH; ++p) d[p] = (h >> (p * D)) & ((1u << D) - 1u);
+  }
+};
+
+// Runs of equal digits are counted in registers first: skewed digits (the
+// exponent byte of float coordinates) would otherwise serialise on one LDS
+// address.
+template <class DG, int D>
+__device__ __forceinline__ void hist_item(const uint32_t* w, uint32_t* s_h, uint32_t (&last)[DG::kPasses],
+                                          uint32_t (&run)[DG::kPasses]) {
+  constexpr int RADIX = 1 << D;
+  uint32_t d[DG::kPasses];
+  DG::digits(w, d);
+#pragma unroll
+  for (int p = 0; p < DG::kPasses; ++p) {
+    if (run[p] != 0 && d[p] == last[p]) {
       ++run[p];
     } else {
       if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
-      last[p] = d;
+      last[p] = d[p];
       run[p] = 1;
     }
   }
 }
 
-template <int K, int D, int BLOCK, int GROUPS>
-__global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t* __restrict__ vtx, int64_t n,
-                                                     uint32_t* __restrict__ hist) {
-  constexpr int RADIX = 1 << D;
-  constexpr int P = (32 * K + D - 1) / D;
-  constexpr int R = 4 / gcd4(K);   // records per group
-  constexpr int GW = R * K;        // words per group (multiple of 4)
-  __shared__ uint32_t s_h[P * RADIX];
-  for (int i = threadIdx.x; i < P * RADIX; i += BLOCK) s_h[i] = 0;
-  __syncthreads();
+// Items per load group: R consecutive items of STRIDE <= 4 words make a
+// whole number of 16-byte vectors, so a wave reads one contiguous stretch per
+// load instruction. Wider items are read one at a time: with several wide
+// items per group (20 to 36 words in registers next to the per-pass run
+// registers) the counts came out wrong on the GPU for 5- to 8-word keys,
+// although the source computes them correctly (see the design notes).
+constexpr int items_per_group(int stride) { return stride <= 4 ? 4 / gcd4(stride) : 1; }
 
-  // Runs of equal digits are counted in registers first: skewed digits (the
-  // exponent byte of float coordinates) would otherwise serialise on one
-  // LDS address.
+// Adds chunk `chunk` (BLOCK * GROUPS item groups) of the n items to the
+// block's LDS histograms `s_h` ([kPasses * RADIX], zeroed by the caller). The
+// one body behind every histogram launch; it touches only LDS, the caller
+// adds s_h to the global histograms once (flush_histograms).
+template <class DG, int K, int D, int STRIDE, int BLOCK, int GROUPS>
+__device__ __forceinline__ void histogram_chunk(const uint32_t* __restrict__ src, int64_t n, uint32_t* s_h,
+                                                int64_t chunk) {
+  constexpr int P = DG::kPasses;
+  constexpr int R = items_per_group(STRIDE);
+  constexpr int GW = R == 1 ? K : R * STRIDE;  // words held per group
   uint32_t last[P], run[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
-
-  // Chunks of BLOCK * GROUPS groups, grid-stride (the launch gives every
-  // chunk its own workgroup: fewer, longer-lived workgroups measured slower).
-  const bool vec = (reinterpret_cast<uintptr_t>(vtx) & 15) == 0;
-  const int64_t groups = (n + R - 1) / R;
-  for (int64_t g0 = int64_t(blockIdx.x) * (BLOCK * GROUPS); g0 < groups;
-       g0 += int64_t(gridDim.x) * (BLOCK * GROUPS))
-  for (int it = 0; it < GROUPS; ++it) {
-    const int64_t g = g0 + int64_t(it) * BLOCK + threadIdx.x;
-    const int64_t r0 = g * R;
-    if (r0 >= n) break;
-    uint32_t w[GW];
-    if (vec && r0 + R <= n) {
-      const uint4* p4 = reinterpret_cast<const uint4*>(vtx + r0 * K);
-#pragma unroll
-      for (int q = 0; q < GW / 4; ++q) {
-        const uint4 x = p4[q];
-        w[4 * q] = x.x; w[4 * q + 1] = x.y; w[4 * q + 2] = x.z; w[4 * q + 3] = x.w;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < GW; ++q) w[q] = (r0 * K + q < n * K) ? vtx[r0 * K + q] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (r0 + r < n) hist_record<K, D>(w + r * K, s_h, last, run);
-  }
-#pragma unroll
-  for (int p = 0; p < P; ++p)
-    if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
-  __syncthreads();
-  for (int i = threadIdx.x; i < P * RADIX; i += BLOCK)
-    if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
-}
-
-// One chunk of BLOCK * GROUPS record groups into the block's LDS histograms
-// `s_h` ([P * RADIX], zeroed), then added to `hist`: the histogram half of
-// the fused used-marking launch, where every chunk has its own workgroup.
-template <int K, int D, int BLOCK, int GROUPS>
-__device__ __forceinline__ void histogram_chunk(const uint32_t* __restrict__ vtx, int64_t n,
-                                                uint32_t* __restrict__ hist, uint32_t* s_h, int64_t chunk) {
-  constexpr int RADIX = 1 << D;
-  constexpr int P = (32 * K + D - 1) / D;
-  constexpr int R = 4 / gcd4(K);
-  constexpr int GW = R * K;
-  uint32_t last[P], run[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
-  const bool vec = (reinterpret_cast<uintptr_t>(vtx) & 15) == 0;
+  const bool vec = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
   for (int it = 0; it < GROUPS; ++it) {
     const int64_t g = chunk * (BLOCK * GROUPS) + int64_t(it) * BLOCK + threadIdx.x;
     const int64_t r0 = g * R;
     if (r0 >= n) break;
     uint32_t w[GW];
-    if (vec && r0 + R <= n) {
-      const uint4* p4 = reinterpret_cast<const uint4*>(vtx + r0 * K);
+    if constexpr (R == 1) {
 #pragma unroll
-      for (int q = 0; q < GW / 4; ++q) {
-        const uint4 x = p4[q];
-        w[4 * q] = x.x; w[4 * q + 1] = x.y; w[4 * q + 2] = x.z; w[4 * q + 3] = x.w;
-      }
+      for (int q = 0; q < K; ++q) w[q] = src[r0 * STRIDE + q];
     } else {
+      if (vec && r0 + R <= n) {
+        const uint4* p4 = reinterpret_cast<const uint4*>(src + r0 * STRIDE);
 #pragma unroll
-      for (int q = 0; q < GW; ++q) w[q] = (r0 * K + q < n * K) ? vtx[r0 * K + q] : 0u;
+        for (int q = 0; q < GW / 4; ++q) {
+          const uint4 x = p4[q];
+          w[4 * q] = x.x; w[4 * q + 1] = x.y; w[4 * q + 2] = x.z; w[4 * q + 3] = x.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < GW; ++q) w[q] = (r0 * STRIDE + q < n * STRIDE) ? src[r0 * STRIDE + q] : 0u;
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (r0 + r < n) hist_record<K, D>(w + r * K, s_h, last, run);
+      if (r0 + r < n) hist_item<DG, D>(w + r * STRIDE, s_h, last, run);
   }
 #pragma unroll
   for (int p = 0; p < P; ++p)
-    if (run[p]) atomicAdd(&s_h[p * RADIX + last[p]], run[p]);
+    if (run[p]) atomicAdd(&s_h[p * (1 << D) + last[p]], run[p]);
+}
+
+template <int WORDS, int BLOCK>
+__device__ __forceinline__ void zero_histograms(uint32_t* s_h) {
+  for (int i = threadIdx.x; i < WORDS; i += BLOCK) s_h[i] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < P * RADIX; i += BLOCK)
+}
+
+template <int WORDS, int BLOCK>
+__device__ __forceinline__ void flush_histograms(const uint32_t* s_h, uint32_t* __restrict__ hist) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < WORDS; i += BLOCK)
     if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// Histogram launch over items that may sit in one of two buffers: src[0],
+// or src[1] when *sel is non-zero; the count is min(n, *n_dev) when n_dev is
+// set (both read on the device: the key sort of the hash grouping learns its
+// input only there).
+struct HistArgs {
+  const uint32_t* src[2];
+  const int32_t* sel;
+  int64_t n;
+  const int64_t* n_dev;
+  uint32_t* hist;
+};
+
+// Every chunk gets its own workgroup (fewer, longer-lived workgroups
+// measured slower); the grid-stride loop only matters for capped grids.
+template <class DG, int K, int D, int STRIDE, int BLOCK, int GROUPS>
+__global__ __launch_bounds__(BLOCK) void k_histogram(HistArgs a) {
+  constexpr int WORDS = DG::kPasses << D;
+  __shared__ uint32_t s_h[WORDS];
+  const int64_t n = a.n_dev ? min(a.n, int64_t(__builtin_amdgcn_readfirstlane(int32_t(*a.n_dev)))) : a.n;
+  const uint32_t* src = (a.sel && __builtin_amdgcn_readfirstlane(*a.sel)) ? a.src[1] : a.src[0];
+  constexpr int R = items_per_group(STRIDE);
+  const int64_t chunks = ((n + R - 1) / R + BLOCK * GROUPS - 1) / (BLOCK * GROUPS);
+  if (int64_t(blockIdx.x) >= chunks) return;  // whole block
+  zero_histograms<WORDS, BLOCK>(s_h);
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x)
+    histogram_chunk<DG, K, D, STRIDE, BLOCK, GROUPS>(src, n, s_h, c);
+  flush_histograms<WORDS, BLOCK>(s_h, a.hist);
 }
 
 // Histograms of the mesh-id passes of a batch: mesh b contributes its vertex
@@ -223,7 +250,9 @@ __global__ void k_mesh_histogram(const int64_t* __restrict__ off, int32_t nmesh,
 // and dead[p] = 1 if one digit holds all n elements in pass p.
 template <int D, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_scan_buckets(uint32_t* __restrict__ hist, int64_t n,
+                                                        const int64_t* __restrict__ n_dev,
                                                         uint32_t* __restrict__ dead) {
+  if (n_dev) n = min(n, *n_dev);
   constexpr int RADIX = 1 << D;
   constexpr int BPT = (RADIX + BLOCK - 1) / BLOCK;
   __shared__ uint32_t s_wave[BLOCK / kWave];
@@ -287,8 +316,11 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   __shared__ uint32_t s_base[RADIX];
   __shared__ __align__(16) uint32_t s_buf[NBUF][TILE];
   // Key passes recompute each element's digit from its reordered words;
-  // mesh passes (whose digit needs a lookup) stage it in LDS.
-  constexpr bool kStageDigits = MODE == kPassMesh;
+  // mesh and hash passes (whose digit costs a lookup or a hash) stage it in
+  // LDS.
+  constexpr bool kFirst = MODE == kPassFirst || MODE == kPassFirstHash;
+  constexpr bool kHash = MODE == kPassFirstHash || MODE == kPassHash;
+  constexpr bool kStageDigits = MODE == kPassMesh || kHash;
   __shared__ uint16_t s_dig[kStageDigits ? TILE : 1];
   __shared__ uint32_t s_wave[WAVES];
   __shared__ uint32_t s_tile;
@@ -298,26 +330,37 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   const int wave = tid / kWave;
   // This pass's plan entry is requested first and examined after the LDS
   // set-up and the block barrier below, so its latency is hidden.
-  const uint32_t entry = MODE == kPassFirst ? 0u : a.bufs.entry(a.pass);
-  if constexpr (MODE == kPassFirst) {
+  const uint32_t entry = kFirst ? 0u : a.bufs.entry(a.pass);
+  // element count (read on the device for the key sort of the hash grouping)
+  const int64_t n = a.n_dev ? min(a.n, int64_t(__builtin_amdgcn_readfirstlane(int32_t(*a.n_dev)))) : a.n;
+  if constexpr (kFirst) {
     if (blockIdx.x == 0 && tid == 0) write_sort_plan(a.bufs);
   }
   for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_hist[i] = 0;
   const uint32_t tile = claim_tile(a.tile_counter, &s_tile);  // synchronises the block
-  if constexpr (MODE != kPassFirst) {
+  // Tiles past the count have no elements: nobody waits on them, and the
+  // next pass (same count) never reads their look-back rows.
+  if (int64_t(tile) * TILE >= n) return;
+  if constexpr (!kFirst) {
     // A pass with a single live digit would leave the order as it is: it
     // moves nothing, and only clears its row of the next pass's look-back
     // buffer.
     if (entry & 2u) {
       if constexpr (!WIDE)
         for (int bin = tid; bin < RADIX; bin += BLOCK)
-          lb_store(lookback_next_of(a.lookback, a.pass, gridDim.x, RADIX) + int64_t(tile) * RADIX + bin, 0u);
+          lb_store(static_cast<uint32_t*>(a.lookback_next) + int64_t(tile) * RADIX + bin, 0u);
       return;
     }
   }
-  const uint32_t* const src = MODE == kPassFirst ? a.vtx : a.bufs.buf[entry & 1u];
+  const uint32_t* const src = kFirst ? a.vtx : a.bufs.buf[entry & 1u];
   const int64_t tile_base = int64_t(tile) * TILE;
-  const int64_t n = a.n;
+  // word masks of the key digit (all-ones for the chosen word), uniform
+  uint32_t lo_mask[K], hi_mask[K];
+#pragma unroll
+  for (int w = 0; w < K; ++w) {
+    lo_mask[w] = w == a.lo_word ? 0xFFFFFFFFu : 0u;
+    hi_mask[w] = w == a.hi_word ? 0xFFFFFFFFu : 0u;
+  }
   const int valid_count = int(min(int64_t(TILE), n - tile_base));
 
   // ---- load
@@ -330,12 +373,15 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // of one byte load per element (the byte loads cost more than the rest of
   // the pass's reads together).
   const uint8_t* s_used = nullptr;
-  if constexpr (MODE == kPassFirst && IPT % 4 == 0) {
+  if constexpr (kFirst && IPT % 4 == 0) {
     uint8_t* stage = reinterpret_cast<uint8_t*>(&s_buf[0][0]) + wave * (kWave * IPT);
     const int64_t chunk = tile_base + int64_t(wave) * (kWave * IPT);
     const int64_t mine = chunk + int64_t(lane) * IPT;
     uint32_t w[IPT / 4];
-    if (mine + IPT <= n) {
+    if (!a.used) {
+#pragma unroll
+      for (int q = 0; q < IPT / 4; ++q) w[q] = 0u;
+    } else if (mine + IPT <= n) {
 #pragma unroll
       for (int q = 0; q < IPT / 4; ++q) w[q] = reinterpret_cast<const uint32_t*>(a.used + mine)[q];
     } else {
@@ -359,10 +405,10 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   for (int j = 0; j < IPT; ++j) {
     const int64_t pos = wave_base + j * kWave;
     if (pos < n) {
-      if constexpr (MODE == kPassFirst) {
+      if constexpr (kFirst) {
 #pragma unroll
         for (int k = 0; k < K; ++k) v[j][k] = src[pos * K + k];
-        const bool used = (IPT % 4 == 0) ? s_used[j * kWave + lane] != 0 : a.used[pos] != 0;
+        const bool used = (IPT % 4 == 0) ? s_used[j * kWave + lane] != 0 : (a.used && a.used[pos] != 0);
         v[j][K] = uint32_t(pos) | (used ? 0x80000000u : 0u);
       } else {
         load_words<S>(src + pos * S, v[j]);
@@ -382,7 +428,10 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
       dig[j] = (m >> a.shift) & MASK;
     } else {
-      dig[j] = masked_digit<D, K>(v[j], a.lo_mask, a.hi_mask, a.shift);
+      if constexpr (kHash)
+        dig[j] = (hash_words<K>(v[j]) >> a.shift) & MASK;
+      else
+        dig[j] = masked_digit<D, K>(v[j], lo_mask, hi_mask, a.shift);
     }
   }
 
@@ -433,7 +482,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
         run += c;
       }
       if constexpr (!WIDE)
-        lb_store(lookback_next_of(a.lookback, a.pass, gridDim.x, RADIX) + int64_t(tile) * RADIX + bin, 0u);
+        lb_store(static_cast<uint32_t*>(a.lookback_next) + int64_t(tile) * RADIX + bin, 0u);
       const uint32_t gend = bin + 1 < RADIX ? a.bucket_base[bin + 1] : uint32_t(n);
       live[k] = gend != a.bucket_base[bin];
       if (live[k]) {
@@ -538,12 +587,12 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
     if constexpr (kStageDigits)
       d = s_dig[q < valid_count ? q : 0];
     else
-      d = masked_digit<D, K>(v[r], a.lo_mask, a.hi_mask, a.shift);
+      d = masked_digit<D, K>(v[r], lo_mask, hi_mask, a.shift);
     opos[r] = q < valid_count ? s_base[d] + uint32_t(q) : 0xFFFFFFFFu;
   }
 
   // ---- scatter: consecutive q of one digit go to consecutive addresses
-  uint32_t* const out = a.bufs.buf[MODE == kPassFirst ? 0u : (entry & 1u) ^ 1u];
+  uint32_t* const out = a.bufs.buf[kFirst ? 0u : (entry & 1u) ^ 1u];
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     if (int64_t(opos[r]) < n) store_words<S>(out + int64_t(opos[r]) * S, v[r]);

@@ -1,0 +1,141 @@
+"""GPU parity of the hash-grouping path (records sorted by a few hash
+digits, equal records grouped in on-chip memory, only the used values sorted
+by their full key) against the oracle, bit for bit, next to the sort-all
+path: small and ragged sizes, every record width, the flags, meshes whose
+heavy duplicates overflow a hash bucket (the device falls back to sorting
+everything), and the full-size workloads."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+HASH = 8       # MRX_TUNING_HASH_GROUPS
+SORT_ALL = 4   # MRX_TUNING_SORT_ALL
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _run(vtx_np, idx_np, flags, tuning=(0, 0, 0)):
+    import paper_2109_09812_amd as mrx
+    v = torch.from_numpy(np.ascontiguousarray(vtx_np).view(np.int32)).to(DEV)
+    i = torch.from_numpy(np.ascontiguousarray(idx_np, dtype=np.int32)).to(DEV)
+    r = mrx.reindex_mesh(v, i, tuning=(*tuning, flags))
+    torch.cuda.synchronize()
+    return (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(), r.old2new.cpu().numpy(),
+            r.new2old.cpu().numpy())
+
+
+def check(vtx_np, idx_np, name, flags=HASH, tuning=(0, 0, 0)):
+    _say(name, "N=%d E=%d A=%d flags=%d tuning=%s" % (vtx_np.shape[0], idx_np.shape[0], idx_np.shape[1], flags,
+                                                      tuning))
+    got = _run(vtx_np, idx_np, flags, tuning)
+    exp = oracle.reindex(vtx_np, idx_np)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
+        assert g.shape == e.shape, (name, label, g.shape, e.shape)
+        assert np.array_equal(g, e), f"{name}: {label} differs at {np.argwhere(g != e)[:5].tolist()}"
+    return got
+
+
+def test_worked_example_and_tiny():
+    x = np.array([1.0, 2.0, 3.0, 7.5, 4.0, 3.0, 5.0, 6.0, 8.5, 4.0], np.float32)
+    vtx = np.stack([x, np.zeros_like(x)], 1)
+    idx = np.array([[0, 1, 2], [0, 2, 4], [5, 6, 7], [5, 7, 9]], np.int32)
+    ov, oi, o2n, n2o = check(vtx, idx, "worked example")
+    assert o2n.tolist() == [0, 1, 2, -1, 3, 2, 4, 5, -1, 3]
+    assert n2o.tolist() == [0, 1, 2, 4, 6, 7]
+    for n in (1, 2, 3, 63, 64, 65, 511, 1365, 2047, 2048, 2049, 3071, 3072, 3073, 6145):
+        vtx, idx = meshgen.random_mesh(n, max(1, n // 2), 3, 3, max(1, n // 3), 500 + n, 0.8)
+        check(vtx, idx, f"tiny{n}")
+
+
+def test_no_elements_and_all_unused():
+    vtx = np.random.default_rng(0).random((70_000, 3), dtype=np.float32)
+    got = check(vtx, np.zeros((0, 3), np.int32), "no elements")
+    assert got[0].shape[0] == 0 and np.all(got[2] == -1)
+
+
+FUZZ = [
+    # n, words, arity, distinct, used_frac, seed
+    (4095, 3, 3, 900, 0.9, 6), (4097, 3, 3, 4097, 0.6, 8), (8191, 2, 4, 3000, 0.9, 9),
+    (8193, 5, 3, 2000, 0.9, 10), (12289, 8, 4, 5000, 0.97, 11), (20000, 12, 3, 700, 0.9, 12),
+    (30001, 16, 2, 9000, 0.8, 13), (100_000, 3, 3, 30_000, 0.95, 14), (300_001, 3, 3, 60_000, 0.9, 15),
+    (250_000, 1, 1, 1_000, 0.5, 16), (150_000, 2, 4, 150_000, 1.0, 17), (99_999, 7, 3, 20_000, 0.9, 18),
+    (1_000_003, 3, 3, 170_000, 0.95, 19), (700_000, 4, 3, 700_000, 0.9, 20), (400_000, 6, 4, 90_000, 0.9, 21),
+]
+
+
+@pytest.mark.parametrize("n,k,a,d,u,seed", FUZZ)
+def test_fuzz(n, k, a, d, u, seed):
+    e = max(1, (n * 2) // (3 * a))
+    vtx, idx = meshgen.random_mesh(n, e, a, k, d, 7000 + seed, u)
+    check(vtx, idx, f"fuzz{seed}")
+
+
+def test_every_record_width():
+    rng = np.random.default_rng(17)
+    for k in range(1, 17):
+        n = int(rng.integers(60_000, 140_000))
+        vtx, idx = meshgen.random_mesh(n, n // 3, 3, k, n // 5, 800 + k, 0.9)
+        check(vtx, idx, f"width{k}")
+
+
+def test_flags_and_tunings():
+    import paper_2109_09812_amd as mrx
+    m = meshgen.grid_soup(300, 0.05, 4321, "hashflags")
+    for fl in (HASH | 1, HASH | 2, HASH | 3):
+        check(m.vtx, m.idx, "soup300 flags", flags=fl)
+    for t in mrx.tunings(12):
+        check(m.vtx, m.idx, "soup300 tuning", flags=HASH, tuning=t.as_tuple())
+
+
+def test_heavy_duplicates_fall_back():
+    """A value with thousands of copies overflows its hash bucket's window:
+    the device takes the sort-all path, with the identical result."""
+    rng = np.random.default_rng(31)
+    n = 200_000
+    vtx = rng.random((n, 3), dtype=np.float32)
+    heavy = rng.choice(n, 6000, replace=False)
+    vtx[heavy] = vtx[heavy[0]]
+    idx = rng.integers(0, n, size=(n // 3, 3)).astype(np.int32)
+    check(vtx, idx, "heavy duplicates")
+    check(np.ones((90_000, 3), np.float32), np.array([[5, 8000, 17]], np.int32), "identical")
+    # an unreferenced heavy value among used ones
+    vtx2 = vtx.copy()
+    idx2 = idx.copy()
+    idx2[np.isin(idx2, heavy)] = 7
+    check(vtx2, idx2, "heavy unused")
+
+
+def test_paper_quads_and_soups():
+    for q in (256, 300):
+        m = meshgen.paper_quads(q)
+        got = check(m.vtx, m.idx, f"quads{q}")
+        assert got[0].shape[0] == (q + 1) ** 2
+    m = meshgen.cfg1()
+    check(m.vtx, m.idx, "soup256")
+
+
+def test_full_size_workloads():
+    for name, make, u in (("tets64", meshgen.cfg3, 65 ** 3), ("soup10M", meshgen.cfg5_mesh, 1251 * 1281)):
+        m = make()
+        got = check(m.vtx, m.idx, name)
+        assert got[0].shape[0] == u
+
+
+def test_hash_and_sort_all_agree_on_soup2048():
+    m = meshgen.cfg2()
+    _say("soup2048 hash vs sort-all")
+    a = _run(m.vtx, m.idx, HASH)
+    b = _run(m.vtx, m.idx, SORT_ALL)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert a[0].shape[0] == 2048 * 2048
