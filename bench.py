@@ -174,7 +174,7 @@ def choose_tuning(args, vtx, idx):
     if tuning is None:
         from paper_2109_09812_amd import autotune
         t, report = autotune.autotune(vtx, idx, reps=3)
-        tuning = t.as_tuple()
+        tuning = t.as_key()
         log(f"autotuned: {tuning} from {report}")
     args.chosen_tuning = tuning
     return tuning
@@ -217,38 +217,66 @@ def bench_single(args, torch, mrx, meshgen):
     log(f"verified ({time.perf_counter() - t0:.1f}s): U={u}")
     extract = bench_extract(args, torch, mrx, m, vtx, idx, u)
 
-    passes = table.get("onesweep", (0, 0.0))
     s_elem = r_bytes + 4
-    pass_bytes = 2 * n * s_elem                     # read + write every element once
-    achieved = pass_bytes / (passes[1] * 1e-3) / 1e9 if passes[0] else None
-    # algorithmic bytes of the sort part of the step (byte model of each kernel)
-    model = {
-        "mark_used": 4 * e * a + e * a,
-        "histogram": n * r_bytes,
-        "onesweep_first": n * r_bytes + n + n * s_elem,
-        "onesweep": pass_bytes,
-    }
-    # the used marking and the histograms run as one launch where they fit
-    model["mark_histogram"] = model["mark_used"] + model["histogram"]
-    step_bytes = model["mark_histogram"] + model["onesweep_first"] + \
-        model["onesweep"] * max(0, passes[0] // max(1, args.steps))
+    mi = e * a
+    # distinct values of the workload: every grid point plus every unused
+    # random vertex (uniform fp32 triples, distinct from each other and from
+    # the grid points)
+    g = u + (n - mi)
+    hashed = "group" in table
+    # algorithmic bytes per launch of each kernel (reads + writes the step
+    # must make; random 1-4 byte accesses counted at their size)
+    if hashed:
+        model = {
+            "mark_histogram": 5 * mi + n * r_bytes,
+            "histogram": u * s_elem,
+            "onesweep_hash_first": n * r_bytes + n + n * s_elem,
+            "onesweep_hash": 2 * n * s_elem,
+            "group": n * s_elem + 8 * n + 4 * g + 4 * (g - u) + u * s_elem,
+            "onesweep": 2 * u * s_elem,
+            "finalize": u * s_elem + u * r_bytes + 12 * u,
+            "old2new": 12 * n + 4 * g,
+            "remap": 12 * mi,
+        }
+    else:
+        model = {
+            "mark_histogram": 5 * mi + n * r_bytes,
+            "mark_used": 5 * mi,
+            "histogram": n * r_bytes,
+            "onesweep_first": n * r_bytes + n + n * s_elem,
+            "onesweep": 2 * n * s_elem,
+            "flag_scan": n * s_elem + 8 * n + g * (r_bytes + 4) + g,
+            "compact": g * (1 + r_bytes + 4) + u * (r_bytes + 4) + 4 * g,
+            "old2new": 12 * n + 4 * g,
+            "remap": 12 * mi,
+        }
     kernels = {name: {"launches_per_step": c // args.steps, "mean_ms": round(t, 5)}
                for name, (c, t) in table.items()}
     for name, b in model.items():
         if name in kernels and table[name][1] > 0:
+            kernels[name]["model_bytes"] = b
             kernels[name]["model_GBps"] = round(b / (table[name][1] * 1e-3) / 1e9, 1)
-    # distinct values of the workload: every grid point plus every unused
-    # random vertex (uniform fp32 triples, distinct from each other and from
-    # the grid points)
-    g = u + (n - e * a)
-    ref_bytes, _ = reference_model_bytes(n, e * a, g, u, r_bytes)
+    run_bytes = sum(b * table[name][0] // args.steps for name, b in model.items() if name in table)
+    # the dominant kernel: the LSD digit pass, every launch of it in the step
+    sweep = [nm for nm in table if nm.startswith("onesweep")]
+    sweep_ms = sum(table[nm][0] * table[nm][1] for nm in sweep)
+    sweep_bytes = sum(table[nm][0] * model.get(nm, 0) for nm in sweep)
+    sweep_launches = sum(table[nm][0] for nm in sweep)
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
+    ref_bytes, _ = reference_model_bytes(n, mi, g, u, r_bytes)
     pipeline = {"model": "Section 2 pipeline with 8-bit LSD digits over all key bits",
                 "model_bytes": ref_bytes, "achieved_GBps": round(ref_bytes / (ms * 1e-3) / 1e9, 1),
-                "frac": round(ref_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4), "groups": g}
+                "frac": round(ref_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4), "groups": g,
+                "strategy": "hash grouping" if hashed else "sort all",
+                # the bytes the kernels that actually ran must move
+                "run_model_bytes": run_bytes,
+                "run_frac": round(run_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)}
     return dict(n=n, m=e * a, u=u, ms=ms, ms_prof=ms_prof, kernels=kernels, extract=extract, dist=dist, xfer=xfer,
                 pipeline=pipeline,
-                roofline_pass=dict(achieved=achieved, bytes=pass_bytes, mean_ms=passes[1]),
-                step_model_bytes_sort=step_bytes, r_bytes=r_bytes)
+                roofline_pass=dict(achieved=achieved, bytes=sweep_bytes // max(1, sweep_launches),
+                                   mean_ms=sweep_ms / max(1, sweep_launches),
+                                   launches_per_step=sweep_launches // args.steps),
+                r_bytes=r_bytes)
 
 
 def bench_batched(args, torch, mrx, meshgen):
@@ -262,7 +290,7 @@ def bench_batched(args, torch, mrx, meshgen):
     eo = torch.from_numpy(b.elem_offsets).to(dev)
     from paper_2109_09812_amd import autotune
     t, report = autotune.autotune(vtx, idx, vo, eo, reps=2)
-    log(f"batch4096: N={n} meshes={b.num_meshes}; autotuned {t.as_tuple()} from {report}; capturing graph")
+    log(f"batch4096: N={n} meshes={b.num_meshes}; autotuned {t.as_key()} from {report}; capturing graph")
     g = mrx.GraphedBatchedReindexer(vtx, vo, idx, eo, tuning=t)
     g.replay()
     torch.cuda.synchronize()
@@ -317,7 +345,7 @@ def bench_batched(args, torch, mrx, meshgen):
             "total_vertices": n, "batched_ms": round(ms_b, 3), "per_mesh_ms": round(ms_p, 3),
             "batched_vertices_per_s": n / (ms_b * 1e-3), "per_mesh_vertices_per_s": n / (ms_p * 1e-3),
             "speedup": round(ms_p / ms_b, 2), "batched_equals_per_mesh": bool(same),
-            "tuning": list(t.as_tuple()),
+            "tuning": list(t.as_key()),
             "closed_form_counts_ok": exp_ok, "merge": merge}
 
 
@@ -450,7 +478,7 @@ def bench_configs(args, torch, mrx, meshgen):
         n = vtx.shape[0]
         row = {"num_vertices": n, "record_bytes": 4 * vtx.shape[1], "unique_out": u,
                "closed_form_ok": u == expected, "ms": round(ms, 4),
-               "vertices_per_s": round(n / (ms * 1e-3)), "tuning": list(t.as_tuple())}
+               "vertices_per_s": round(n / (ms * 1e-3)), "tuning": list(t.as_key())}
         if name.startswith("paper_quads"):
             q = int(name[len("paper_quads"):])
             row["paper_rtx3090_ms"] = PAPER_GPU_MS[q]
@@ -532,7 +560,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tuning", type=str, default=None, help="digit_bits,block,items e.g. 8,256,16")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="digit_bits,block,items[,flags] e.g. 8,256,16,8 (flags 8: hash grouping, 4: sort all)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gather", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -593,12 +622,12 @@ def main():
                                "(25,141,254 referenced + 5% unused), 8,380,418 int32 triangles, permuted",
                    "num_vertices": n, "num_indices": single["m"], "unique_out": single["u"],
                    "record_bytes": single["r_bytes"], "tuning": list(args.chosen_tuning)},
-        "roofline": {"bound": "hbm", "kernel": "k_onesweep (one LSD digit pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_onesweep (LSD digit pass; every launch of the step)",
                      "achieved": round(rp["achieved"], 1) if rp["achieved"] else None,
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(rp["achieved"] / PEAK_HBM_GBPS, 4) if rp["achieved"] else None,
                      "traffic": measured_traffic(), "bytes_per_launch": rp["bytes"],
-                     "mean_launch_ms": rp["mean_ms"],
+                     "mean_launch_ms": rp["mean_ms"], "launches_per_step": rp["launches_per_step"],
                      # the whole step against the roofline: the plain method's
                      # algorithmic bytes for this workload / step time / peak
                      "pipeline_frac": single["pipeline"]["frac"],

@@ -46,6 +46,10 @@ class Tuning(ctypes.Structure):
         """The kernel shape (flags excluded)."""
         return (self.digit_bits, self.block_threads, self.items_per_thread)
 
+    def as_key(self):
+        """The kernel shape and the flags."""
+        return (self.digit_bits, self.block_threads, self.items_per_thread, self.flags)
+
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32

@@ -1,8 +1,11 @@
 """Autotuner for the radix-sort kernel shape (digit width, workgroup size,
-items per thread).
+items per thread) and, for single meshes, the way duplicates are found
+(sort all vertices by their full record, or hash grouping).
 
-Every compiled variant computes the identical result, so tuning is purely a
-speed choice. For a given workload shape the tuner runs every variant once,
+Every compiled variant and either strategy compute the identical result, so
+tuning is purely a speed choice. Which strategy wins depends on the data (how
+many copies each value has), so the tuner times both on the caller's mesh.
+For a given workload shape the tuner runs every candidate once,
 checks its outputs bit for bit against variant 0's (a variant that differs is
 a bug and raises), times a few launches with HIP events, and keeps the
 fastest. Results are cached in a JSON file keyed by GPU architecture, record
@@ -24,7 +27,7 @@ import torch
 from . import _lib
 from .api import BatchedReindexer, Reindexer
 
-SCHEMA = 1
+SCHEMA = 2
 
 
 def cache_path() -> str:
@@ -69,15 +72,32 @@ def save_cache(entries: dict, path: str | None = None):
     os.replace(tmp, path)
 
 
+_STRATEGY_FLAGS = (_lib.MRX_TUNING_SORT_ALL, _lib.MRX_TUNING_HASH_GROUPS)
+
+
+def candidates(vtx_bytes: int, num_vtx: int, batched: bool):
+    """Every compiled kernel shape, with each strategy a call of this shape
+    can take (batches and meshes of 2^30 or more vertices always sort all)."""
+    flags = (0,) if batched or num_vtx >= (1 << 30) else _STRATEGY_FLAGS
+    out = []
+    for t in _lib.tunings(vtx_bytes):
+        for fl in flags:
+            out.append(_lib.Tuning(t.digit_bits, t.block_threads, t.items_per_thread, fl))
+    return out
+
+
 def cached_tuning(entries: dict, key: str, vtx_bytes: int):
-    """The cached variant for `key` if the loaded library still has it, else None."""
+    """The cached candidate for `key` if the loaded library still has its
+    shape and its flags are a strategy choice, else None."""
     e = entries.get(key)
-    if not isinstance(e, dict) or not isinstance(e.get("tuning"), list) or len(e["tuning"]) != 3:
+    if not isinstance(e, dict) or not isinstance(e.get("tuning"), list) or len(e["tuning"]) != 4:
         return None
     want = tuple(int(x) for x in e["tuning"])
+    if want[3] not in (0,) + _STRATEGY_FLAGS:
+        return None
     for t in _lib.tunings(vtx_bytes):
-        if t.as_tuple() == want:
-            return t
+        if t.as_tuple() == want[:3]:
+            return _lib.Tuning(*want)
     return None
 
 
@@ -108,10 +128,11 @@ def _time(launch, reps: int) -> float:
 def autotune(vtx: torch.Tensor, idx: torch.Tensor, vtx_offsets: torch.Tensor | None = None,
              elem_offsets: torch.Tensor | None = None, *, reps: int = 5, use_cache: bool = True,
              path: str | None = None, verbose: bool = False):
-    """Pick the fastest compiled sort variant for this workload shape.
+    """Pick the fastest candidate (compiled sort variant and strategy) for
+    this workload shape.
 
     Returns (tuning, report) where report maps each candidate (d, block,
-    items) to its median milliseconds."""
+    items, flags) to its median milliseconds."""
     batched = vtx_offsets is not None
     vtx_bytes = 4 * vtx.shape[1]
     key = shape_key(_arch(vtx.device), vtx_bytes, vtx.shape[0], batched)
@@ -123,7 +144,7 @@ def autotune(vtx: torch.Tensor, idx: torch.Tensor, vtx_offsets: torch.Tensor | N
     ref = None
     report = {}
     best = None
-    for t in _lib.tunings(vtx_bytes):
+    for t in candidates(vtx_bytes, vtx.shape[0], batched):
         if batched:
             r = BatchedReindexer(vtx, vtx_offsets, idx, elem_offsets, tuning=t)
         else:
@@ -134,17 +155,17 @@ def autotune(vtx: torch.Tensor, idx: torch.Tensor, vtx_offsets: torch.Tensor | N
         if ref is None:
             ref = [o.clone() for o in outs]
         elif not all(torch.equal(a, b) for a, b in zip(ref, outs)):
-            raise RuntimeError(f"sort variant {t.as_tuple()} disagrees with variant 0")
+            raise RuntimeError(f"candidate {t.as_key()} disagrees with the first one")
         ms = _time(r.launch, reps)
-        report[t.as_tuple()] = ms
+        report[t.as_key()] = ms
         if verbose:
-            print(f"[autotune] {key} {t.as_tuple()}: {ms:.4f} ms", flush=True)
+            print(f"[autotune] {key} {t.as_key()}: {ms:.4f} ms", flush=True)
         if best is None or ms < best[1]:
             best = (t, ms)
         del r
     if use_cache:
         entries = load_cache(path)
-        entries[key] = {"tuning": list(best[0].as_tuple()), "ms": best[1],
+        entries[key] = {"tuning": list(best[0].as_key()), "ms": best[1],
                         "candidates": {",".join(map(str, k)): v for k, v in report.items()}}
         save_cache(entries, path)
     return best[0], report

@@ -230,45 +230,68 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
   for (int i = 0; i < IPT; ++i)
     if (head[i]) s_scratch[slot[i]] = gbelow[i];
 
-  // ---- look-back across chunks: groups and used groups before this chunk
-  if (tid == 0) {
+  // ---- look-back across chunks: groups and used groups before this chunk.
+  // Wave 0 reads 64 predecessors' words per step (lane l: chunk hi - l), so a
+  // walk over chunks that have only published their own counts takes one
+  // round trip per 64 chunks.
+  if (wave == 0) {
     const uint32_t g_own = active ? gt : 0u, u_own = active ? ut : 0u, o_own = over ? 1u : 0u;
     uint64_t* lb = a.lookback + tile;
     uint32_t gp = 0, up = 0, op = 0;
     if (tile == 0) {
-      lb_store(lb, GroupLb::pack(kLbInclusive, g_own, u_own, o_own));
+      if (lane == 0) lb_store(lb, GroupLb::pack(kLbInclusive, g_own, u_own, o_own));
     } else {
-      lb_store(lb, GroupLb::pack(kLbAggregate, g_own, u_own, o_own));
-      int64_t t = int64_t(tile) - 1;
+      if (lane == 0) lb_store(lb, GroupLb::pack(kLbAggregate, g_own, u_own, o_own));
+      int64_t hi = int64_t(tile) - 1;
       uint32_t spins = 0;
-      while (t >= 0) {
-        const uint64_t w = lb_load(a.lookback + t);
+      while (true) {
+        const int64_t t = hi - lane;
+        // below chunk 0: a virtual inclusive prefix of zero
+        const uint64_t w = t >= 0 ? lb_load(a.lookback + t) : GroupLb::pack(kLbInclusive, 0, 0, 0);
         const uint32_t st = GroupLb::status(w);
-        if (st == 0) {
+        const uint64_t incl = ballot(st == kLbInclusive);
+        const uint64_t none = ballot(st == 0);
+        // lanes up to and including the nearest inclusive prefix
+        const int stop = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
+        const uint64_t upto = stop == kWave - 1 ? ~uint64_t(0) : ((uint64_t(1) << (stop + 1)) - 1);
+        if (none & upto) {  // a predecessor that counts has not published yet
           if (++spins >= kSpinLimit || flag_load(&a.ctl->abort)) {
-            __hip_atomic_store(&a.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
+            if (lane == 0) {
+              __hip_atomic_store(&a.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
+            }
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        gp += GroupLb::groups(w);
-        up += GroupLb::used(w);
-        op |= GroupLb::over(w);
-        if (st == kLbInclusive) break;
-        --t;
+        const bool mine = (upto >> lane) & 1u;
+        uint32_t g = mine ? GroupLb::groups(w) : 0u, u = mine ? GroupLb::used(w) : 0u;
+        uint32_t o = mine ? GroupLb::over(w) : 0u;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+          g += __shfl_xor(g, off, kWave);
+          u += __shfl_xor(u, off, kWave);
+          o |= __shfl_xor(o, off, kWave);
+        }
+        gp += g;
+        up += u;
+        op |= o;
+        if (incl) break;
+        hi -= kWave;
       }
-      lb_store(lb, GroupLb::pack(kLbInclusive, gp + g_own, up + u_own, op | o_own));
+      if (lane == 0) lb_store(lb, GroupLb::pack(kLbInclusive, gp + g_own, up + u_own, op | o_own));
     }
-    s_gpre = gp;
-    s_upre = up;
-    if (tile == gridDim.x - 1) {
-      const uint32_t any_over = op | o_own;
-      a.ctl->num_groups = int64_t(gp) + g_own;
-      a.ctl->num_used = int64_t(up) + u_own;
-      a.ctl->path = int32_t(any_over);
-      a.ctl->sort_count = any_over ? n : int64_t(up) + u_own;
+    if (lane == 0) {
+      s_gpre = gp;
+      s_upre = up;
+      if (tile == gridDim.x - 1) {
+        const uint32_t any_over = op | o_own;
+        a.ctl->num_groups = int64_t(gp) + g_own;
+        a.ctl->num_used = int64_t(up) + u_own;
+        a.ctl->path = int32_t(any_over);
+        a.ctl->sort_count = any_over ? n : int64_t(up) + u_own;
+      }
     }
   }
   __syncthreads();

@@ -63,13 +63,18 @@ void launch_hist(const uint32_t* vtx, int64_t n, uint32_t* hist, hipStream_t s) 
 }
 
 // Key-digit histograms of sort elements (K + 1 words) whose buffer and count
-// are read on the device; the grid covers a.n (the capacity).
+// are read on the device. The grid covers a.n (the capacity), capped at two
+// workgroups per CU: each workgroup then walks several chunks before it adds
+// its LDS histograms to the global ones once (with one chunk per workgroup
+// those additions, one per nonzero bin, cost more than the counting).
+constexpr int64_t kElemHistGrid = 512;
+
 template <int D>
 void launch_elem_hist(const HistArgs& a, hipStream_t s) {
   constexpr int B = 256, GROUPS = kHistGroups;
   constexpr int R = items_per_group(K + 1);
   const int64_t per_block = int64_t(B) * GROUPS * R;
-  const int64_t grid = (a.n + per_block - 1) / per_block;
+  const int64_t grid = std::min<int64_t>((a.n + per_block - 1) / per_block, kElemHistGrid);
   if (grid > 0)
     hipLaunchKernelGGL((k_histogram<KeyDigits<K, D>, K, D, K + 1, B, GROUPS>), dim3(grid), dim3(B), 0, s, a);
 }

@@ -249,13 +249,23 @@ def test_autotune_cache_validation(tmp_path, monkeypatch):
     json.dump({"schema": at.SCHEMA, "abi": 999, "entries": {"k": {}}}, open(path, "w"))
     assert at.load_cache(path) == {}                       # other ABI
     t0 = _lib.tunings(12)[0].as_tuple()
-    entries = {"a": {"tuning": list(t0)}, "b": {"tuning": [7, 333, 5]}, "c": {"tuning": "x"}}
+    hashed = _lib.MRX_TUNING_HASH_GROUPS
+    entries = {"a": {"tuning": list(t0) + [hashed]}, "b": {"tuning": [7, 333, 5, 0]}, "c": {"tuning": "x"},
+               "d": {"tuning": list(t0)}, "e": {"tuning": list(t0) + [1]}}
     at.save_cache(entries, path)
     loaded = at.load_cache(path)
     assert loaded == json.loads(json.dumps(entries))
-    assert at.cached_tuning(loaded, "a", 12).as_tuple() == t0
+    assert at.cached_tuning(loaded, "a", 12).as_key() == t0 + (hashed,)
     assert at.cached_tuning(loaded, "b", 12) is None       # variant not in the library
     assert at.cached_tuning(loaded, "c", 12) is None       # malformed
+    assert at.cached_tuning(loaded, "d", 12) is None       # no strategy (older schema)
+    assert at.cached_tuning(loaded, "e", 12) is None       # flags that are not a strategy choice
+    # candidates: every shape with both strategies for a single mesh, shapes only for a batch
+    single = at.candidates(12, 100_000, False)
+    assert len(single) == 2 * len(_lib.tunings(12))
+    assert {t.flags for t in single} == {_lib.MRX_TUNING_SORT_ALL, hashed}
+    assert {t.flags for t in at.candidates(12, 100_000, True)} == {0}
+    assert {t.flags for t in at.candidates(12, 1 << 30, False)} == {0}
     assert at.cached_tuning(loaded, "missing", 12) is None
     k = at.shape_key("gfx950", 12, 26_398_316, False)
     assert k == "gfx950|R=12|n=2^25|single"

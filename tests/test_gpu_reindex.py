@@ -242,16 +242,21 @@ def test_paper_quads():
         assert got[0].shape[0] == (q + 1) ** 2
 
 
+SORT_ALL = (0, 0, 0, 4)   # MRX_TUNING_SORT_ALL: Section 2's sort of every vertex
+
+
 def test_cfg3_tets_full():
     m = meshgen.cfg3()
-    got = assert_parity(m.vtx, m.idx, name="tets64")
-    assert got[0].shape[0] == 65 ** 3
+    for t in (None, SORT_ALL):
+        got = assert_parity(m.vtx, m.idx, tuning=t, name="tets64")
+        assert got[0].shape[0] == 65 ** 3
 
 
 def test_cfg5_soup10m_full():
     m = meshgen.cfg5_mesh()
-    got = assert_parity(m.vtx, m.idx, name="soup10M")
-    assert got[0].shape[0] == 1251 * 1281
+    for t in (None, SORT_ALL):
+        got = assert_parity(m.vtx, m.idx, tuning=t, name="soup10M")
+        assert got[0].shape[0] == 1251 * 1281
 
 
 def test_cfg2_soup2048_full():
@@ -279,9 +284,9 @@ def test_autotune_picks_a_verified_variant(tmp_path):
     v, i = to_dev(m.vtx, m.idx)
     _say("autotune")
     t, report = autotune.autotune(v, i, reps=2, path=str(tmp_path / "t.json"))
-    assert t.as_tuple() in report and len(report) == len(mrx.tunings(12))
+    assert t.as_key() in report and len(report) == 2 * len(mrx.tunings(12))
     t2, rep2 = autotune.autotune(v, i, reps=2, path=str(tmp_path / "t.json"))
-    assert t2.as_tuple() == t.as_tuple() and "cached" in rep2
+    assert t2.as_key() == t.as_key() and "cached" in rep2
     got = gpu(m.vtx, m.idx, tuning=t)
     exp = oracle.reindex(m.vtx, m.idx)
     for g, e in zip(got, exp):
