@@ -256,6 +256,16 @@ def bench_single(args, torch, mrx, meshgen):
         if name in kernels and table[name][1] > 0:
             kernels[name]["model_bytes"] = b
             kernels[name]["model_GBps"] = round(b / (table[name][1] * 1e-3) / 1e9, 1)
+    if hashed and (args.chosen_tuning[0] in (0, 8)):
+        # key passes of the used values whose digit is the same for every used
+        # value are skipped and move nothing (read off the sorted output;
+        # counted for 8-bit digits)
+        ow = res.out_vtx.cpu().numpy().view("uint32").reshape(u, k)
+        passes = 4 * k
+        dead = sum(1 for p in range(passes)
+                   if u == 0 or np.all(((ow[:, k - 1 - p // 4] >> np.uint32(8 * (p % 4))) & np.uint32(255)) ==
+                                       ((ow[0, k - 1 - p // 4] >> np.uint32(8 * (p % 4))) & np.uint32(255))))
+        model["onesweep"] = model["onesweep"] * (passes - dead) // passes   # average over the launches
     run_bytes = sum(b * table[name][0] // args.steps for name, b in model.items() if name in table)
     # the dominant kernel: the LSD digit pass, every launch of it in the step
     sweep = [nm for nm in table if nm.startswith("onesweep")]
@@ -298,16 +308,50 @@ def bench_batched(args, torch, mrx, meshgen):
     ms_b, _ = timed_steps(g.replay, reps, torch)
     res = g.result()
     log(f"batched graph replay: {ms_b:.3f} ms")
+    # per-kernel view: the same launch sequence outside the graph, with the
+    # library's timing events
+    from paper_2109_09812_amd import _lib
+    br = mrx.BatchedReindexer(vtx, vo, idx, eo, tuning=t)
+    br.launch()
+    torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    ms_bp, _ = timed_steps(br.launch, reps, torch)
+    btable = kernel_table(_lib.profile_records())
+    _lib.profile_enable(False)
+    del br
+    bkernels = {name: {"launches_per_launch": c // reps, "mean_ms": round(ms_, 4)} for name, (c, ms_) in btable.items()}
+    # the plain method's bytes, mesh by mesh (distinct values of a patch soup:
+    # its grid points plus its unused random vertices)
+    sizes_v = np.diff(b.vtx_offsets)
+    sizes_i = np.diff(b.elem_offsets) * 3
+    ref_b = 0
+    for nb, mb, ub in zip(sizes_v.tolist(), sizes_i.tolist(), b.expected_unique.tolist()):
+        ref_b += reference_model_bytes(nb, mb, ub + (nb - mb), ub, 12)[0]
+    batched_pipeline = {"model": "Section 2 pipeline per mesh, 8-bit LSD digits over all key bits",
+                        "model_bytes": int(ref_b), "frac": round(ref_b / (ms_b * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)}
 
     # per-mesh launches: one mrx_reindex_mesh per mesh on one stream, shared
-    # workspace, outputs at the mesh's own offsets, no synchronisation
+    # workspace, outputs at the mesh's own offsets, no synchronisation; each
+    # mesh with the tuning the autotuner picks for its size bucket (tuned on
+    # the bucket's largest mesh)
     from paper_2109_09812_amd import _lib
     lib = _lib.load()
     vo_h, eo_h = b.vtx_offsets, b.elem_offsets
-    maxn = int((vo_h[1:] - vo_h[:-1]).max())
-    maxm = int((eo_h[1:] - eo_h[:-1]).max()) * 3
-    wsb = mrx.workspace_size(maxn, 12, maxm)
+    sizes = np.diff(vo_h)
+    arch = autotune._arch(dev)
+    bucket_of = [autotune.shape_key(arch, 12, int(sz), False) for sz in sizes]
+    bucket_tuning = {}
+    for key in sorted(set(bucket_of)):
+        big = max((i for i in range(b.num_meshes) if bucket_of[i] == key), key=lambda i: sizes[i])
+        v0, v1, e0, e1 = int(vo_h[big]), int(vo_h[big + 1]), int(eo_h[big]), int(eo_h[big + 1])
+        bt, _ = autotune.autotune(vtx[v0:v1], idx[e0:e1], reps=2)
+        bucket_tuning[key] = bt
+    log("per-mesh bucket tunings: " + ", ".join(f"{k.split('|')[2]}:{t.as_key()}"
+                                                for k, t in sorted(bucket_tuning.items())))
+    wsb = max(mrx.workspace_size(int(sizes[i]), 12, int(eo_h[i + 1] - eo_h[i]) * 3, 1, bucket_tuning[bucket_of[i]])
+              for i in range(b.num_meshes))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    tptr = {k: _lib.make_tuning(t) for k, t in bucket_tuning.items()}
     out_vtx = torch.empty_like(vtx)
     out_idx = torch.empty_like(idx)
     o2n = torch.empty(n, dtype=torch.int32, device=dev)
@@ -323,7 +367,7 @@ def bench_batched(args, torch, mrx, meshgen):
                       ctypes.c_void_p(out_vtx.data_ptr() + 12 * v0), ctypes.c_void_p(out_idx.data_ptr() + 12 * e0),
                       ctypes.c_void_p(o2n.data_ptr() + 4 * v0), ctypes.c_void_p(n2o.data_ptr() + 4 * v0),
                       ctypes.c_void_p(counts.data_ptr() + 8 * i), ctypes.c_void_p(status.data_ptr() + 4 * i),
-                      ctypes.c_void_p(ws.data_ptr()), wsb, None, stream))
+                      ctypes.c_void_p(ws.data_ptr()), wsb, tptr[bucket_of[i]], stream))
     f = lib.mrx_reindex_mesh
 
     def per_mesh():
@@ -332,8 +376,9 @@ def bench_batched(args, torch, mrx, meshgen):
 
     per_mesh()
     torch.cuda.synchronize()
-    ms_p, _ = timed_steps(per_mesh, 1, torch)
-    log(f"per-mesh launches: {ms_p:.3f} ms")
+    per_reps = [timed_steps(per_mesh, 1, torch)[0] for _ in range(3)]
+    ms_p = float(np.median(per_reps))
+    log(f"per-mesh launches: {ms_p:.3f} ms (median of {per_reps})")
     same = (torch.equal(out_idx, res.out_idx) and torch.equal(o2n, res.old2new) and
             torch.equal(counts, res.out_vtx_offsets[1:] - res.out_vtx_offsets[:-1]) and
             int(status.abs().sum()) == 0)
@@ -343,6 +388,10 @@ def bench_batched(args, torch, mrx, meshgen):
     merge = bench_merge(args, torch, mrx, b, vtx, vo, idx, eo)
     return {"workload": "batch4096: 4096 soups, log-uniform [100, 200000] triangles, 5% unused",
             "total_vertices": n, "batched_ms": round(ms_b, 3), "per_mesh_ms": round(ms_p, 3),
+            "per_mesh_reps_ms": [round(x, 3) for x in per_reps],
+            "pipeline_frac": batched_pipeline["frac"], "pipeline": batched_pipeline,
+            "kernels": bkernels, "ms_profiled": round(ms_bp, 3),
+            "per_mesh_tunings": {k.split("|")[2]: list(t.as_key()) for k, t in sorted(bucket_tuning.items())},
             "batched_vertices_per_s": n / (ms_b * 1e-3), "per_mesh_vertices_per_s": n / (ms_p * 1e-3),
             "speedup": round(ms_p / ms_b, 2), "batched_equals_per_mesh": bool(same),
             "tuning": list(t.as_key()),
@@ -387,18 +436,33 @@ def bench_extract(args, torch, mrx, mesh, vtx, idx, u_full):
 
 
 def bench_merge(args, torch, mrx, b, vtx, vo, idx, eo):
-    """Section 3 merge of the whole batch4096 into one mesh."""
-    m = mrx.MeshMerger(vtx, vo, idx, eo)
+    """Section 3 merge of the whole batch4096 into one mesh, with each
+    strategy (the overlapping patches give grid points thousands of copies,
+    which overflow the hash grouping's buckets: it falls back to sorting
+    everything); the faster one is the reported time."""
+    from paper_2109_09812_amd import _lib
+    times = {}
+    for name, fl in (("sort_all", _lib.MRX_TUNING_SORT_ALL), ("hash_groups", _lib.MRX_TUNING_HASH_GROUPS)):
+        m = mrx.MeshMerger(vtx, vo, idx, eo, tuning=(0, 0, 0, fl))
+        m.launch()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        times[name], _ = timed_steps(m.launch, reps, torch)
+        del m
+        torch.cuda.empty_cache()
+    best = min(times, key=times.get)
+    m = mrx.MeshMerger(vtx, vo, idx, eo, tuning=(0, 0, 0, _lib.MRX_TUNING_SORT_ALL if best == "sort_all"
+                                                  else _lib.MRX_TUNING_HASH_GROUPS))
     m.launch()
     torch.cuda.synchronize()
-    reps = max(1, min(args.steps, 5))
-    ms, _ = timed_steps(m.launch, reps, torch)
+    ms = times[best]
     r = m.result()
     mesh_of_elem = np.repeat(np.arange(b.num_meshes), np.diff(b.elem_offsets))
     glob = b.idx.astype(np.int64) + b.vtx_offsets[mesh_of_elem][:, None]
     ok = _sampled_records_ok(b.vtx, glob, r.out_idx, r.out_vtx, r.new2old, np.random.default_rng(7))
     n = vtx.shape[0]
-    out = {"workload": "batch4096 merged into one mesh", "ms": round(ms, 3),
+    out = {"workload": "batch4096 merged into one mesh", "ms": round(ms, 3), "strategy": best,
+           "ms_by_strategy": {k: round(v, 3) for k, v in times.items()},
            "vertices_per_s": n / (ms * 1e-3), "unique_out": r.num_out,
            "fewer_than_per_mesh": bool(r.num_out < int(b.expected_unique.sum())), "sampled_records_ok": ok}
     log("merge", out)
@@ -555,6 +619,25 @@ def kernels_only(args, torch, mrx, meshgen):
                       "copy_probe_bytes_each_way": a.numel() * 4, "unique_out": rx.result().num_out}))
 
 
+def batched_kernels_only(args, torch, mrx, meshgen):
+    """Profiler target: W + K launches of the 4096-mesh batch (no graph, so
+    every kernel shows up on its own)."""
+    b = meshgen.cfg4()
+    dev = torch.device("cuda:0")
+    vtx = torch.from_numpy(b.vtx.view("int32")).to(dev)
+    vo = torch.from_numpy(b.vtx_offsets).to(dev)
+    idx = torch.from_numpy(b.idx).to(dev)
+    eo = torch.from_numpy(b.elem_offsets).to(dev)
+    tuning = args.tuning or (8, 256, 16, 0)
+    r = mrx.BatchedReindexer(vtx, vo, idx, eo, tuning=tuning)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup + args.steps):
+        r.launch()
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "batched-kernels", "steps": args.steps, "warmup": args.warmup,
+                      "tuning": list(tuning), "total_vertices": int(b.vtx.shape[0])}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -566,8 +649,9 @@ def main():
     ap.add_argument("--no-gather", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' re-index times")
-    ap.add_argument("--mode", choices=("full", "kernels"), default="full",
-                    help="kernels: only the timed re-index steps and a 1 GiB copy probe (for profilers)")
+    ap.add_argument("--mode", choices=("full", "kernels", "batched-kernels"), default="full",
+                    help="kernels: only the timed re-index steps and a 1 GiB copy probe (for profilers); "
+                         "batched-kernels: only W + K launches of the 4096-mesh batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X "
@@ -584,6 +668,9 @@ def main():
 
     if args.mode == "kernels":
         kernels_only(args, torch, mrx, meshgen)
+        return
+    if args.mode == "batched-kernels":
+        batched_kernels_only(args, torch, mrx, meshgen)
         return
     single = bench_single(args, torch, mrx, meshgen)
     extras = {}
