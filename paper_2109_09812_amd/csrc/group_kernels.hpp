@@ -41,6 +41,9 @@ struct GroupShape {
   static constexpr int TS = 1 << TB;
   // average bucket size the host aims for when it picks the hash passes
   static constexpr int TARGET_BUCKET = CHUNK / 4;
+  // waves per SIMD the register budget is set for: three workgroups per CU
+  // (LDS: keys of the window + the table, at most 53 KB each)
+  static constexpr int MIN_WAVES_PER_SIMD = 3 * (BLOCK / 64) / 4;
   static_assert(WIN % BLOCK == 0, "window positions per thread");
   static_assert(TS * 3 >= WIN * 4, "table load");
 };
@@ -82,7 +85,7 @@ __device__ __forceinline__ bool lds_keys_equal(const uint32_t* s_keys, int a, in
 }
 
 template <int K>
-__global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
+__global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_SIMD) void k_group(GroupArgs a) {
   using SH = GroupShape<K>;
   constexpr int S = SH::S, BLOCK = SH::BLOCK, WIN = SH::WIN, CHUNK = SH::CHUNK, IPT = SH::IPT;
   constexpr int TS = SH::TS, TB = SH::TB;
@@ -92,7 +95,6 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
   constexpr int kScratch = WIN > TS ? WIN : TS;
 
   __shared__ uint32_t s_keys[K * WIN];      // window records, word-major
-  __shared__ uint32_t s_ids[WIN];           // window ids (bit 31: referenced)
   __shared__ uint32_t s_scratch[kScratch];  // buckets of the window, then the table
   __shared__ uint32_t s_cnt[2][IPT][WAVES];
   __shared__ uint32_t s_tile, s_sq, s_eq;
@@ -109,8 +111,11 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
   const int64_t c1 = min(n, c0 + CHUNK);
   const int qc1 = int(c1 - c0) + 1;  // window slot of position c1
 
-  // ---- window: positions c0 - 1 + q, q in [0, WIN)
-  uint32_t hv[IPT];
+  // ---- window: positions c0 - 1 + q, q in [0, WIN). Each thread keeps, for
+  // its own slots, the id (bit 31: referenced) and, until the table is
+  // built, the record's hash in `slot`; everything else lives in LDS, so
+  // that three workgroups fit on a CU.
+  uint32_t ids[IPT], slot[IPT];
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const int q = i * BLOCK + tid;
@@ -124,9 +129,9 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
     }
 #pragma unroll
     for (int w = 0; w < K; ++w) s_keys[w * WIN + q] = e[w];
-    s_ids[q] = e[K];
-    hv[i] = hash_words<K>(e);
-    s_scratch[q] = hv[i] & a.bucket_mask;
+    ids[i] = e[K];
+    slot[i] = hash_words<K>(e);
+    s_scratch[q] = slot[i] & a.bucket_mask;
   }
   __syncthreads();
 
@@ -152,13 +157,13 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
 
   // ---- one table entry per distinct record of the owned span [sq, eq):
   // the smallest window slot holding it (its first copy), bit 31 = used
-  uint32_t slot[IPT];
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const int q = i * BLOCK + tid;
+    const uint32_t h = slot[i];
     slot[i] = kEmpty;
     if (!active || q < sq || q >= eq) continue;
-    uint32_t sl = (hv[i] * 0x9E3779B1u) >> (32 - TB);
+    uint32_t sl = (h * 0x9E3779B1u) >> (32 - TB);
     for (int probe = 0; probe < TS; ++probe) {
       uint32_t cur = s_scratch[sl];
       if (cur == kEmpty) {
@@ -177,28 +182,26 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
     }
   }
   __syncthreads();
-  bool head[IPT];
+  uint32_t headm = 0;  // bit i: slot i of this thread holds its group's first copy
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const int q = i * BLOCK + tid;
-    head[i] = false;
     if (slot[i] == kEmpty) continue;
-    head[i] = (s_scratch[slot[i]] & 0xFFFFu) == uint32_t(q);
-    if (s_ids[q] & kUsedBit) atomicOr(&s_scratch[slot[i]], kUsedBit);
+    if ((s_scratch[slot[i]] & 0xFFFFu) == uint32_t(q)) headm |= 1u << i;
+    if (ids[i] & kUsedBit) atomicOr(&s_scratch[slot[i]], kUsedBit);
   }
   __syncthreads();
 
   // ---- number the groups (and the used ones) in window order: slot q =
   // i * BLOCK + tid, so round i of every wave precedes round i + 1
-  bool uhead[IPT];
-  uint32_t gbelow[IPT], ubelow[IPT];
+  uint32_t uheadm = 0;  // bit i: a head whose group is used
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    uhead[i] = head[i] && (s_scratch[slot[i]] & kUsedBit) != 0u;
-    const uint64_t hm = ballot(head[i]);
-    const uint64_t um = ballot(uhead[i]);
-    gbelow[i] = uint32_t(popc64(hm & lanemask_lt()));
-    ubelow[i] = uint32_t(popc64(um & lanemask_lt()));
+    const bool h = (headm >> i) & 1u;
+    const bool uh = h && (s_scratch[slot[i]] & kUsedBit) != 0u;
+    uheadm |= uh ? (1u << i) : 0u;
+    const uint64_t hm = ballot(h);
+    const uint64_t um = ballot(uh);
     if (lane == 0) {
       s_cnt[0][i][wave] = uint32_t(popc64(hm));
       s_cnt[1][i][wave] = uint32_t(popc64(um));
@@ -208,27 +211,26 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
   uint32_t gt = 0, ut = 0;  // totals of the window
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    uint32_t wg = 0, wu = 0;
+    uint32_t gb = gt, ub = ut;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
       const uint32_t cg = s_cnt[0][i][w], cu = s_cnt[1][i][w];
       if (w < wave) {
-        wg += cg;
-        wu += cu;
+        gb += cg;
+        ub += cu;
       }
+      gt += cg;
+      ut += cu;
     }
-    gbelow[i] += gt + wg;
-    ubelow[i] += ut + wu;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      gt += s_cnt[0][i][w];
-      ut += s_cnt[1][i][w];
-    }
+    const bool h = (headm >> i) & 1u;
+    const uint64_t hm = ballot(h);
+    const uint64_t um = ballot((uheadm >> i) & 1u);
+    gb += uint32_t(popc64(hm & lanemask_lt()));
+    ub += uint32_t(popc64(um & lanemask_lt()));
+    // heads leave their group's rank (low half) and used rank (high half)
+    // in the table for the other copies; both are below WIN <= 2^16
+    if (h) s_scratch[slot[i]] = gb | (ub << 16);
   }
-  // heads leave their group's rank in the table for the other copies
-#pragma unroll
-  for (int i = 0; i < IPT; ++i)
-    if (head[i]) s_scratch[slot[i]] = gbelow[i];
 
   // ---- look-back across chunks: groups and used groups before this chunk.
   // Wave 0 reads 64 predecessors' words per step (lane l: chunk hi - l), so a
@@ -304,17 +306,18 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK) void k_group(GroupArgs a) {
     if (slot[i] == kEmpty) continue;
     const int q = i * BLOCK + tid;
     const int64_t pos = c0 - 1 + q;
-    const uint32_t g = gpre + s_scratch[slot[i]];
-    const uint32_t org = s_ids[q] & 0x7FFFFFFFu;
+    const uint32_t ranks = s_scratch[slot[i]];
+    const uint32_t g = gpre + (ranks & 0xFFFFu);
+    const uint32_t org = ids[i] & 0x7FFFFFFFu;
     if (int64_t(g) >= n || pos < 0 || pos >= n) {  // only after a failed wait
       atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
       continue;
     }
     a.pairs[pos] = make_uint2(g, org);
-    if (!head[i]) continue;
+    if (!((headm >> i) & 1u)) continue;
     a.rep[g] = int32_t(org);
-    if (uhead[i]) {
-      const uint32_t u = upre + ubelow[i];
+    if ((uheadm >> i) & 1u) {
+      const uint32_t u = upre + (ranks >> 16);
       if (int64_t(u) >= n) {
         atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
         continue;
