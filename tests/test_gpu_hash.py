@@ -139,3 +139,49 @@ def test_hash_and_sort_all_agree_on_soup2048():
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     assert a[0].shape[0] == 2048 * 2048
+
+
+def _capture(launch):
+    """Capture one launch into a graph (after an eager warm-up on a side stream)."""
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=DEV)
+    side.wait_stream(torch.cuda.current_stream(DEV))
+    with torch.cuda.stream(side):
+        launch()
+    torch.cuda.current_stream(DEV).wait_stream(side)
+    with torch.cuda.graph(g):
+        launch()
+    return g
+
+
+def test_graph_replays_switch_between_grouping_and_fallback():
+    """One captured hash-grouping launch sequence replayed on contents that
+    alternately group in LDS and overflow a bucket (a value with 6,000
+    copies): the device picks the path on every replay, and every replay
+    equals the oracle."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(4040)
+    n = 120_000
+    base = rng.random((n, 3), dtype=np.float32)
+    idx_np = rng.integers(0, n, size=(n // 3, 3)).astype(np.int32)
+    v = torch.from_numpy(base.view(np.int32).copy()).to(DEV)
+    i = torch.from_numpy(idx_np).to(DEV)
+    rx = mrx.Reindexer(v, i, tuning=(0, 0, 0, HASH))
+    g = _capture(rx.launch)
+    for rep in range(4):
+        vtx = base.copy()
+        if rep % 2:
+            heavy = rng.choice(n, 6000, replace=False)
+            vtx[heavy] = vtx[heavy[0]]
+        else:
+            vtx[rng.choice(n, n // 4, replace=False)] = vtx[rng.choice(n, n // 4)]
+        v.copy_(torch.from_numpy(vtx.view(np.int32)))
+        _say("graph replay", rep, "heavy" if rep % 2 else "grouped")
+        g.replay()
+        r = rx.result()
+        got = (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(), r.old2new.cpu().numpy(),
+               r.new2old.cpu().numpy())
+        exp = oracle.reindex(vtx, idx_np)
+        for label, gg, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
+            assert np.array_equal(gg, e), f"replay {rep}: {label}"
+        _ = (v.float() * 2).sum().item()
