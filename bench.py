@@ -229,6 +229,9 @@ def bench_single(args, torch, mrx, meshgen):
     if hashed:
         model = {
             "mark_histogram": 5 * mi + n * r_bytes,
+            "band_partition": 8 * mi,
+            "band_mark": 4 * mi + n,
+            "hash_histogram": n * r_bytes,
             "histogram": u * s_elem,
             "onesweep_hash_first": n * r_bytes + n + n * s_elem,
             "onesweep_hash": 2 * n * s_elem,

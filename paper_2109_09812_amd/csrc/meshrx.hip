@@ -362,6 +362,30 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   return MRX_OK;
 }
 
+// Step 1 by vertex bands (k_band_partition, k_band_mark) where the vertex
+// range splits into at most kMaxBands bands whose flags fit a workgroup's
+// LDS, there are enough entries to pay for two launches, and the partitioned
+// entries plus the band table fit in one sort buffer (s words per vertex).
+constexpr int64_t kBandMinEntries = int64_t(1) << 16;
+struct BandPlan {
+  bool use = false;
+  int shift = 0, nb = 0;
+  int64_t tiles = 0;
+};
+BandPlan band_plan(int64_t n, int64_t m, int s) {
+  BandPlan b;
+  if (n <= 0 || m < kBandMinEntries) return b;
+  int shift = kMinBandShift;
+  while (((n - 1) >> shift) + 1 > kMaxBands) ++shift;
+  if (shift > kMaxBandShift) return b;
+  b.shift = shift;
+  b.nb = int(((n - 1) >> shift) + 1);
+  b.tiles = (m + kBandTile - 1) / kBandTile;
+  const int64_t part_words = (m + 63) / 64 * 64;
+  b.use = part_words + int64_t(b.nb) * b.tiles <= n * int64_t(s);
+  return b;
+}
+
 // The hash-grouping launch sequence of one mesh (see group_kernels.hpp):
 //   Step 1 (marking) with the hash-digit histograms; stable sort of
 //   (record, id | used << 31) by P_hash hash digits into X; grouping of each
@@ -372,7 +396,8 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
 //   the fallback path, Section 2's flag scan and compaction; the old2new
 //   scatter and the index remap (Step 4) are shared.
 // Buffers: A and B hold the hash passes (X = the last one written, Y = the
-// other), C the used groups; the key sort alternates between X and C.
+// other), C the used groups (before the grouping: Step 1's partitioned
+// entries and band table); the key sort alternates between X and C.
 mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, int64_t num_vtx,
                        int32_t vtx_bytes, const int32_t* idx, int64_t num_elems, int32_t arity,
                        const int64_t* live_elems, void* out_vtx, int32_t* out_idx, int32_t* old2new,
@@ -414,10 +439,23 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
                        reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
                        static_cast<int64_t*>(nullptr));
   }
-  // Step 1 and the hash-digit histograms
+  // Step 1 and the hash-digit histograms: by vertex bands (partitioned
+  // entries and band table in C, which the grouping fills only later), else
+  // scattered byte stores beside the histograms
+  const BandPlan bp = band_plan(n, m, L.S);
   const MarkArgs mark{idx, m, arity, n, nullptr, nullptr, 0, nullptr, live_elems, used_v, status};
-  prof_mark(m > 0 ? "mark_histogram" : "histogram", s);
-  v.hash_hist(m > 0 ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
+  if (bp.use) {
+    const int64_t part_words = (m + 63) / 64 * 64;
+    const BandArgs ba{idx, m, arity, n, live_elems, bp.shift, bp.nb, aligned(idx, 16) ? 1 : 0, bp.tiles,
+                      reinterpret_cast<int32_t*>(buf[2]), buf[2] + part_words, used_v, status};
+    prof_mark("band_partition", s);
+    hipLaunchKernelGGL(k_band_partition, dim3(bp.tiles), dim3(kBandBlock), 0, s, ba);
+    prof_mark("band_mark", s);
+    hipLaunchKernelGGL(k_band_mark, dim3(bp.nb), dim3(kBandMarkBlock), 0, s, ba);
+  }
+  const bool fused_mark = m > 0 && !bp.use;
+  prof_mark(fused_mark ? "mark_histogram" : "hash_histogram", s);
+  v.hash_hist(fused_mark ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
   if (n > 0) {
     // stable sort by the hash digits; every hash pass runs (dead flags go to
     // a word nobody reads), so the elements end in X = buf[(ph - 1) & 1]

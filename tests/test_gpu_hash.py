@@ -185,3 +185,57 @@ def test_graph_replays_switch_between_grouping_and_fallback():
         for label, gg, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
             assert np.array_equal(gg, e), f"replay {rep}: {label}"
         _ = (v.float() * 2).sum().item()
+
+
+def test_band_marking_shapes():
+    """Step 1 by vertex bands (at least 65,536 index entries on the hash
+    path): ragged vertex counts around the band-size steps, entries crowded
+    into one band (slices longer than a wave), an index array that is only
+    4-byte aligned, a vertex that is never referenced at each band edge."""
+    rng = np.random.default_rng(77)
+    for n, m, lo_hi, name in ((70_000, 3 * 65_536, (0, 4096), "one band"),
+                              (1_048_577, 3 * 400_000, None, "shift 13, ragged last band"),
+                              (300_001, 3 * 30_000, None, "few entries per band"),
+                              (262_144, 3 * 87_381 + 3, None, "ragged last tile")):
+        vtx = rng.integers(0, 1 << 20, (n, 3), dtype=np.uint32).view(np.float32)
+        vtx[rng.integers(0, n, n // 3)] = vtx[rng.integers(0, n, n // 3)]  # duplicates
+        if lo_hi is None:
+            idx = rng.integers(0, n, m, dtype=np.int64)
+        else:
+            idx = rng.integers(*lo_hi, m, dtype=np.int64)
+        idx = idx.astype(np.int32)
+        edges = np.arange(0, n, 4096)          # first vertex of each 4096-band: unused
+        idx[np.isin(idx, edges)] = 1
+        check(vtx, idx.reshape(-1, 3), name)
+    # index array at a 4-byte (not 16-byte) offset
+    n, m = 150_000, 3 * 40_000
+    vtx = rng.random((n, 3), dtype=np.float32)
+    flat = torch.from_numpy(rng.integers(0, n, m + 1, dtype=np.int64).astype(np.int32)).to(DEV)
+    idx_dev = flat[1:].view(-1, 3)
+    assert idx_dev.data_ptr() % 16 != 0
+    import paper_2109_09812_amd as mrx
+    _say("unaligned index array")
+    r = mrx.reindex_mesh(torch.from_numpy(vtx.view(np.int32)).to(DEV), idx_dev, tuning=(0, 0, 0, HASH))
+    exp = oracle.reindex(vtx, flat[1:].cpu().numpy().reshape(-1, 3))
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"),
+                           (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(),
+                            r.old2new.cpu().numpy(), r.new2old.cpu().numpy()), exp):
+        assert np.array_equal(g, e), label
+
+
+@pytest.mark.parametrize("pos", [0, 8191, 8192, 3 * 70_000 - 1])
+def test_band_marking_reports_bad_index(pos):
+    """An out-of-range entry anywhere in a band-marked call (first and last
+    entry of a tile, last entry) raises; a following call is unaffected."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(pos)
+    n = 100_000
+    vtx = rng.random((n, 3), dtype=np.float32)
+    for bad in (-1, n, 2**31 - 1):
+        idx = rng.integers(0, n, 3 * 70_000).astype(np.int32)
+        idx[pos] = bad
+        _say("bad index", bad, "at", pos)
+        with pytest.raises(IndexError):
+            mrx.reindex_mesh(torch.from_numpy(vtx.view(np.int32)).to(DEV),
+                             torch.from_numpy(idx.reshape(-1, 3)).to(DEV), tuning=(0, 0, 0, HASH))
+    check(vtx, rng.integers(0, n, (70_000, 3)).astype(np.int32), "after the error")
