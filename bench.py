@@ -240,6 +240,13 @@ def bench_single(args, torch, mrx, meshgen):
             "finalize": u * s_elem + u * r_bytes + 12 * u,
             "old2new": 12 * n + 4 * g,
             "remap": 12 * mi,
+            # Step 4 by vertex bands: pairs in, (new id, vertex) entries out;
+            # per band: its entries and index entries in, old2new and the
+            # entries' new ids out; per index tile: slot entries and new ids
+            # in, out_idx out
+            "pair_partition": 8 * n + 4 * n + 8 * n,
+            "band_map": 8 * n + 4 * mi + 4 * n + 4 * mi,
+            "band_remap": 12 * mi,
         }
     else:
         model = {

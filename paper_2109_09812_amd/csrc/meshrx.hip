@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/meshrx.h"
+#include "band_kernels.hpp"
 #include "edit_kernels.hpp"
 #include "registry.hpp"
 
@@ -187,15 +188,54 @@ int hash_passes(int64_t n, const SortVariant& v) {
   return std::max(1, std::min(3, (bits + v.D - 1) / v.D));
 }
 
+// Steps 1 and 4 by vertex bands (band_kernels.hpp) on the hash-grouping
+// path. kMarkOnly: the marking alone (the index partition in buffer C);
+// kMarkAndMap: the marking, old2new and the remap, with the index partition
+// in out_idx (its slots become the remapped tiles) and the new ids of the
+// entries in C. Chosen when there are enough entries to pay for the extra
+// launches, at most kMaxBands bands of at most 2^kMaxMarkShift (marking) or
+// 2^kMaxMapShift (map) vertices, and C holds m words.
+enum BandMode { kBandNone = 0, kMarkOnly = 1, kMarkAndMap = 2 };
+constexpr int64_t kBandMinEntries = int64_t(1) << 16;
+struct BandPlan {
+  int mode = kBandNone;
+  int shift = 0, nb = 0;
+  int64_t itiles = 0, ptiles = 0;
+  size_t words() const {  // index table + tile counts (+ pair table)
+    if (mode == kBandNone) return 0;
+    return size_t(nb) * size_t(itiles) + size_t(itiles) + (mode == kMarkAndMap ? size_t(nb) * size_t(ptiles) : 0);
+  }
+};
+BandPlan band_plan(int64_t n, int64_t m, int s) {
+  BandPlan b;
+  if (n <= 0 || m < kBandMinEntries || m > n * int64_t(s)) return b;
+  int want = kMinBandShift;  // about 256 bands where the band size allows it
+  while (((n - 1) >> want) + 1 > 256) ++want;
+  for (int mode : {int(kMarkAndMap), int(kMarkOnly)}) {
+    const int shift = std::min(want, mode == kMarkAndMap ? kMaxMapShift : kMaxMarkShift);
+    const int64_t nb = ((n - 1) >> shift) + 1;
+    if (nb > kMaxBands) continue;
+    b.mode = mode;
+    b.shift = shift;
+    b.nb = int(nb);
+    b.itiles = (m + kBandTile - 1) / kBandTile;
+    b.ptiles = mode == kMarkAndMap ? (n + kPairTile - 1) / kPairTile : 0;
+    return b;
+  }
+  return b;
+}
+
 struct Layout {
   int K = 0, S = 0, P_key = 0, P_mesh = 0, P_hash = 0;  // P_hash > 0: hash grouping
+  BandPlan band;                                         // hash grouping only
   int64_t tiles_sort = 0, tiles_scan = 0, tiles_group = 0;
   // zeroed region
   size_t ctl = 0, counters = 0, hist = 0, plan = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0,
          used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_lookback = 0, zero_end = 0;
   int64_t tiles_elem = 0;
   // scratch
-  size_t buf_a = 0, buf_b = 0, buf_c = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, total = 0;
+  size_t buf_a = 0, buf_b = 0, buf_c = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, band_tab = 0,
+         total = 0;
   int64_t vtx_tab_n = 0, elem_tab_n = 0;
 };
 
@@ -243,6 +283,8 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   if (L.P_hash) {
     L.buf_c = off;  off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
+    L.band = band_plan(n, num_idx, L.S);
+    L.band_tab = off; off = align_up(off + sizeof(uint32_t) * L.band.words());
   }
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
   L.rep = off;      off = align_up(off + sizeof(int32_t) * size_t(n));
@@ -362,30 +404,6 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
   return MRX_OK;
 }
 
-// Step 1 by vertex bands (k_band_partition, k_band_mark) where the vertex
-// range splits into at most kMaxBands bands whose flags fit a workgroup's
-// LDS, there are enough entries to pay for two launches, and the partitioned
-// entries plus the band table fit in one sort buffer (s words per vertex).
-constexpr int64_t kBandMinEntries = int64_t(1) << 16;
-struct BandPlan {
-  bool use = false;
-  int shift = 0, nb = 0;
-  int64_t tiles = 0;
-};
-BandPlan band_plan(int64_t n, int64_t m, int s) {
-  BandPlan b;
-  if (n <= 0 || m < kBandMinEntries) return b;
-  int shift = kMinBandShift;
-  while (((n - 1) >> shift) + 1 > kMaxBands) ++shift;
-  if (shift > kMaxBandShift) return b;
-  b.shift = shift;
-  b.nb = int(((n - 1) >> shift) + 1);
-  b.tiles = (m + kBandTile - 1) / kBandTile;
-  const int64_t part_words = (m + 63) / 64 * 64;
-  b.use = part_words + int64_t(b.nb) * b.tiles <= n * int64_t(s);
-  return b;
-}
-
 // The hash-grouping launch sequence of one mesh (see group_kernels.hpp):
 //   Step 1 (marking) with the hash-digit histograms; stable sort of
 //   (record, id | used << 31) by P_hash hash digits into X; grouping of each
@@ -396,8 +414,10 @@ BandPlan band_plan(int64_t n, int64_t m, int s) {
 //   the fallback path, Section 2's flag scan and compaction; the old2new
 //   scatter and the index remap (Step 4) are shared.
 // Buffers: A and B hold the hash passes (X = the last one written, Y = the
-// other), C the used groups (before the grouping: Step 1's partitioned
-// entries and band table); the key sort alternates between X and C.
+// other), C the used groups (before the grouping: Step 1's index partition
+// when only the marking goes by bands); the key sort alternates between X
+// and C; by bands, Step 4 then partitions the pairs into X and puts the
+// index entries' new ids in C.
 mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, int64_t num_vtx,
                        int32_t vtx_bytes, const int32_t* idx, int64_t num_elems, int32_t arity,
                        const int64_t* live_elems, void* out_vtx, int32_t* out_idx, int32_t* old2new,
@@ -442,18 +462,22 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
   // Step 1 and the hash-digit histograms: by vertex bands (partitioned
   // entries and band table in C, which the grouping fills only later), else
   // scattered byte stores beside the histograms
-  const BandPlan bp = band_plan(n, m, L.S);
+  const BandPlan& bp = L.band;
   const MarkArgs mark{idx, m, arity, n, nullptr, nullptr, 0, nullptr, live_elems, used_v, status};
-  if (bp.use) {
-    const int64_t part_words = (m + 63) / 64 * 64;
-    const BandArgs ba{idx, m, arity, n, live_elems, bp.shift, bp.nb, aligned(idx, 16) ? 1 : 0, bp.tiles,
-                      reinterpret_cast<int32_t*>(buf[2]), buf[2] + part_words, used_v, status};
+  uint32_t* band_tab = reinterpret_cast<uint32_t*>(ws + L.band_tab);
+  uint32_t* ipart = bp.mode == kMarkAndMap ? reinterpret_cast<uint32_t*>(out_idx) : buf[2];
+  uint32_t* itable = band_tab;
+  uint32_t* itile_valid = itable + size_t(bp.nb) * size_t(bp.itiles);
+  uint32_t* ptable = itile_valid + bp.itiles;
+  if (bp.mode != kBandNone) {
+    const BandArgs ba{idx, m, arity, n, live_elems, bp.shift, bp.nb, aligned(idx, 16) ? 1 : 0,
+                      bp.mode == kMarkAndMap ? 1 : 0, bp.itiles, ipart, itable, itile_valid, used_v, status};
     prof_mark("band_partition", s);
-    hipLaunchKernelGGL(k_band_partition, dim3(bp.tiles), dim3(kBandBlock), 0, s, ba);
+    launch_band_partition(ba, s);
     prof_mark("band_mark", s);
-    hipLaunchKernelGGL(k_band_mark, dim3(bp.nb), dim3(kBandMarkBlock), 0, s, ba);
+    launch_band_mark(ba, bp.mode == kMarkAndMap, s);
   }
-  const bool fused_mark = m > 0 && !bp.use;
+  const bool fused_mark = m > 0 && bp.mode == kBandNone;
   prof_mark(fused_mark ? "mark_histogram" : "hash_histogram", s);
   v.hash_hist(fused_mark ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
   if (n > 0) {
@@ -575,7 +599,25 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
     c.gate = kGateSortAll;
     prof_mark("compact", s);
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
-    // both paths: Step 4's map
+    // both paths: Step 4's map (and, by bands, the remap)
+    if (bp.mode == kMarkAndMap) {
+      // X and C are free again: X takes the partitioned pairs, C the new ids
+      // of the index entries
+      const PairPartArgs pa{static_cast<const uint2*>(pairs), cmap, n, bp.shift, bp.nb, bp.ptiles,
+                            reinterpret_cast<uint2*>(X), ptable, status};
+      prof_mark("pair_partition", s);
+      launch_pair_partition(pa, s);
+      const BandMapArgs ma{reinterpret_cast<const uint2*>(X), ptable, bp.ptiles, ipart, itable, bp.itiles, n,
+                           bp.shift, old2new, reinterpret_cast<int32_t*>(buf[2])};
+      prof_mark("band_map", s);
+      launch_band_map(ma, bp.nb, s);
+      const BandRemapArgs ra{ipart, reinterpret_cast<const int32_t*>(buf[2]), itile_valid, m, arity, live_elems,
+                             out_idx};
+      prof_mark("band_remap", s);
+      launch_band_remap(ra, bp.itiles, s);
+      prof_mark(nullptr, s);
+      return check_launch();
+    }
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
                        sbk, static_cast<const uint2*>(pairs), cmap, n, nullptr, nullptr, 0, nullptr, old2new);

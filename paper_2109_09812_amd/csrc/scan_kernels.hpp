@@ -68,157 +68,6 @@ __global__ __launch_bounds__(kRandBlock) void k_mark_used(MarkArgs a) {
   mark_used_tile<BATCHED>(a, blockIdx.x);
 }
 
-// Step 1 by vertex bands (one mesh). A scattered byte store costs one fabric
-// request however little it writes, so where the vertex range splits into at
-// most kMaxBands bands of 2^shift vertices whose flags fit one workgroup's
-// LDS as a bitmap, the marking streams instead:
-//  * k_band_partition: a tile of kBandTile index entries groups its valid
-//    entries by band in LDS and writes them band after band into its own
-//    slot part[tile * kBandTile, ...); table[band][tile] = offset << 16 | count
-//    within the slot.
-//  * k_band_mark: one workgroup per band walks its row of the table, sets the
-//    referenced vertices' bits in an LDS bitmap and writes every flag of the
-//    band, 0 or 1, with 16-byte stores (no zeroing needed).
-// Out-of-range entries are dropped and reported, as by mark_used_tile.
-constexpr int kBandBlock = 256;
-constexpr int kBandItems = 32;
-constexpr int kBandTile = kBandBlock * kBandItems;  // offsets and counts fit 16 bits
-constexpr int kMaxBands = kBandBlock;               // one band counter per thread
-constexpr int kBandMarkBlock = 1024;
-constexpr int kMinBandShift = 12;                   // bands start 16-byte aligned
-constexpr int kMaxBandShift = 19;                   // 64 KB bitmap
-
-struct BandArgs {
-  const int32_t* idx;          // [m] index entries
-  int64_t m;                   // capacity in entries (num_elems * arity)
-  int32_t arity;
-  int64_t n;                   // vertices
-  const int64_t* live_elems;   // device, nullable: only the first *live_elems elements count
-  int32_t shift;               // band of vertex v = v >> shift
-  int32_t nb;                  // ceil(n / 2^shift) <= kMaxBands
-  int32_t vec;                 // idx is 16-byte aligned
-  int64_t tiles;               // ceil(m / kBandTile)
-  int32_t* part;               // [m]: each tile's valid entries, grouped by band
-  uint32_t* table;             // [nb][tiles]
-  uint8_t* used;               // [n], 16-byte aligned
-  int32_t* status;
-};
-
-static __global__ __launch_bounds__(kBandBlock) void k_band_partition(BandArgs a) {
-  static_assert(kBandItems % 4 == 0, "entries are loaded four at a time");
-  __shared__ uint32_t s_cnt[kMaxBands];
-  __shared__ uint32_t s_off[kMaxBands];
-  __shared__ int32_t s_stage[kBandTile];
-  __shared__ uint32_t s_wave[kBandBlock / kWave];
-  const int tid = threadIdx.x;
-  s_cnt[tid] = 0;
-  __syncthreads();
-  const int64_t m = a.live_elems ? min(a.m, *a.live_elems * a.arity) : a.m;
-  const int64_t tile = blockIdx.x;
-  const int64_t base = tile * kBandTile;
-  // entry 4 * (i * kBandBlock + tid) + c of the tile goes to v[4 * i + c]
-  int32_t v[kBandItems];
-  if (a.vec && base + kBandTile <= m) {
-    const int4* p = reinterpret_cast<const int4*>(a.idx + base);
-#pragma unroll
-    for (int i = 0; i < kBandItems / 4; ++i) {
-      const int4 q = stream_load(p + i * kBandBlock + tid);
-      v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < kBandItems / 4; ++i)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t k = base + 4 * (int64_t(i) * kBandBlock + tid) + c;
-        v[4 * i + c] = k < m ? stream_load(a.idx + k) : -1;
-      }
-  }
-  bool bad = false;
-#pragma unroll
-  for (int i = 0; i < kBandItems; ++i) {
-    const int64_t k = base + 4 * (int64_t(i / 4) * kBandBlock + tid) + (i % 4);
-    if (k < m && (v[i] < 0 || int64_t(v[i]) >= a.n)) {
-      bad = true;
-      v[i] = -1;
-    }
-  }
-  if (bad) atomicMax(a.status, kErrIndex);
-  uint32_t r[kBandItems];
-#pragma unroll
-  for (int i = 0; i < kBandItems; ++i)
-    if (v[i] >= 0) r[i] = atomicAdd(&s_cnt[v[i] >> a.shift], 1u);
-  __syncthreads();
-  const uint32_t c = s_cnt[tid];
-  uint32_t valid;
-  const uint32_t ex = block_exclusive_scan<kBandBlock>(c, s_wave, &valid);
-  s_off[tid] = ex;
-  if (tid < a.nb) a.table[size_t(tid) * size_t(a.tiles) + size_t(tile)] = (ex << 16) | c;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kBandItems; ++i)
-    if (v[i] >= 0) s_stage[s_off[v[i] >> a.shift] + r[i]] = v[i];
-  __syncthreads();
-  for (uint32_t j = tid; j < valid; j += kBandBlock) stream_store(a.part + base + j, s_stage[j]);
-}
-
-__device__ __forceinline__ uint32_t spread_bits4(uint32_t x) {  // bit i -> byte i (i < 4)
-  return (x & 1u) | ((x & 2u) << 7) | ((x & 4u) << 14) | ((x & 8u) << 21);
-}
-
-static __global__ __launch_bounds__(kBandMarkBlock) void k_band_mark(BandArgs a) {
-  constexpr int WAVES = kBandMarkBlock / kWave;
-  constexpr int BATCH = 16;  // table entries whose slices are loaded at once
-  __shared__ uint32_t s_bits[(1 << kMaxBandShift) / 32];
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  const int words = (1 << a.shift) / 32;
-  for (int w = tid; w < words; w += kBandMarkBlock) s_bits[w] = 0;
-  __syncthreads();
-  const int64_t band = blockIdx.x;
-  const int64_t lo = band << a.shift;
-  const uint32_t* row = a.table + size_t(band) * size_t(a.tiles);
-  for (int64_t t0 = int64_t(wave) * kWave; t0 < a.tiles; t0 += int64_t(WAVES) * kWave) {
-    const uint32_t mine = t0 + lane < a.tiles ? row[t0 + lane] : 0u;
-    for (int j0 = 0; j0 < kWave; j0 += BATCH) {
-      int32_t val[BATCH];
-      uint32_t e[BATCH];  // offset << 16 | count of tile t0 + j0 + u
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) {
-        e[u] = __shfl(mine, j0 + u, kWave);
-        // 32-bit positions: part holds m < 2^31 entries
-        const uint32_t at = uint32_t(t0 + j0 + u) * kBandTile + (e[u] >> 16) + lane;
-        val[u] = uint32_t(lane) < (e[u] & 0xFFFFu) ? stream_load(a.part + at) : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u)
-        if (val[u] >= 0) {
-          const uint32_t l = uint32_t(val[u] - lo);
-          atomicOr(&s_bits[l >> 5], 1u << (l & 31));
-        }
-      // slices longer than a wave (rare for spread-out indices)
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) {
-        const uint32_t at = uint32_t(t0 + j0 + u) * kBandTile + (e[u] >> 16);
-        for (uint32_t k = lane + kWave; k < (e[u] & 0xFFFFu); k += kWave) {
-          const uint32_t l = uint32_t(a.part[at + k] - lo);
-          atomicOr(&s_bits[l >> 5], 1u << (l & 31));
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const int64_t hi = min(a.n, lo + (int64_t(1) << a.shift));
-  for (int64_t q = lo + int64_t(tid) * 16; q < hi; q += int64_t(kBandMarkBlock) * 16) {
-    const uint32_t w = (s_bits[(q - lo) >> 5] >> ((q - lo) & 31)) & 0xFFFFu;
-    if (q + 16 <= hi) {
-      const uint4 o = {spread_bits4(w), spread_bits4(w >> 4), spread_bits4(w >> 8), spread_bits4(w >> 12)};
-      stream_store(reinterpret_cast<uint4*>(a.used + q), o);
-    } else {
-      for (int64_t t = q; t < hi; ++t) a.used[t] = uint8_t((w >> (t - q)) & 1u);
-    }
-  }
-}
-
 // ----------------------------------------------------------------------------
 // Step 2 (flags and prefix sum) fused with the scatter of Step 3.
 // Over the sorted elements: head(i) = i == 0 || key(i) != key(i-1) (or, for a

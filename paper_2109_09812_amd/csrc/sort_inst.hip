@@ -92,8 +92,11 @@ void launch_hash_hist_ph(const MarkArgs* ma, const uint32_t* vtx, int64_t n, uin
     hipLaunchKernelGGL((k_mark_histogram<HashDigits<K, D, PH>, K, D, B, GROUPS, false>), dim3(ht + mt), dim3(B),
                        0, s, *ma, vtx, n, hist, ht, mt);
   } else if (ht > 0) {
+    // a few digits per record: the per-workgroup flush of every nonzero bin
+    // outweighs the counting of one chunk, so workgroups walk several chunks
     const HistArgs a{{vtx, vtx}, nullptr, n, nullptr, hist};
-    hipLaunchKernelGGL((k_histogram<HashDigits<K, D, PH>, K, D, K, B, GROUPS>), dim3(ht), dim3(B), 0, s, a);
+    hipLaunchKernelGGL((k_histogram<HashDigits<K, D, PH>, K, D, K, B, GROUPS>), dim3(std::min(ht, kElemHistGrid)),
+                       dim3(B), 0, s, a);
   }
 }
 
