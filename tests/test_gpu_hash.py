@@ -239,3 +239,68 @@ def test_band_marking_reports_bad_index(pos):
             mrx.reindex_mesh(torch.from_numpy(vtx.view(np.int32)).to(DEV),
                              torch.from_numpy(idx.reshape(-1, 3)).to(DEV), tuning=(0, 0, 0, HASH))
     check(vtx, rng.integers(0, n, (70_000, 3)).astype(np.int32), "after the error")
+
+
+def test_band_map_in_place_and_unaligned_old2new():
+    """Step 4 by vertex bands writes out_idx over the index partition it kept
+    there: in place (idx is out_idx) and into an old2new that is only 4-byte
+    aligned (the band slices are then stored word by word)."""
+    import ctypes
+
+    import paper_2109_09812_amd as mrx
+    from paper_2109_09812_amd import _lib
+    m = meshgen.grid_soup(300, 0.05, 4242, "band-inplace")
+    _say("band map in place", m.vtx.shape[0])
+    v = torch.from_numpy(m.vtx.view(np.int32)).to(DEV)
+    i = torch.from_numpy(m.idx).to(DEV)
+    r = mrx.reindex_mesh(v, i.clone(), tuning=(0, 0, 0, HASH), in_place=True)
+    exp = oracle.reindex(m.vtx, m.idx)
+    got = (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(), r.old2new.cpu().numpy(),
+           r.new2old.cpu().numpy())
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
+        assert np.array_equal(g, e), label
+    _say("band map, old2new at a 4-byte offset")
+    n, k = m.vtx.shape
+    lib = _lib.load()
+    out_vtx = torch.empty_like(v)
+    out_idx = torch.empty_like(i)
+    o2n_buf = torch.full((n + 4,), -7, dtype=torch.int32, device=DEV)
+    n2o = torch.empty(n, dtype=torch.int32, device=DEV)
+    meta = torch.zeros(2, dtype=torch.int64, device=DEV)
+    tun = _lib.make_tuning((0, 0, 0, HASH))
+    wsb = mrx.workspace_size(n, 4 * k, i.numel(), 1, (0, 0, 0, HASH))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
+    o2n_ptr = o2n_buf.data_ptr() + 4
+    assert o2n_ptr % 16 != 0
+    st = lib.mrx_reindex_mesh(
+        ctypes.c_void_p(v.data_ptr()), n, 4 * k, ctypes.c_void_p(i.data_ptr()), i.shape[0], i.shape[1],
+        ctypes.c_void_p(out_vtx.data_ptr()), ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(o2n_ptr),
+        ctypes.c_void_p(n2o.data_ptr()), ctypes.c_void_p(meta.data_ptr()),
+        ctypes.c_void_p(meta.data_ptr() + 8), ctypes.c_void_p(ws.data_ptr()), wsb, tun,
+        ctypes.c_void_p(torch.cuda.current_stream(DEV).cuda_stream))
+    _lib.check(st, "mrx_reindex_mesh")
+    torch.cuda.synchronize()
+    assert int(meta[1]) == 0
+    o2n = o2n_buf.cpu().numpy()
+    assert o2n[0] == -7 and np.all(o2n[n + 1:] == -7)
+    assert np.array_equal(o2n[1:n + 1], exp[2])
+    assert np.array_equal(out_idx.cpu().numpy(), exp[1])
+
+
+def test_band_marking_only_beyond_map_bands():
+    """More than 2^25 vertices: the old2new slices of 2^15 vertices would
+    need more bands than one table holds, so only the marking goes by
+    (larger) bands and Step 4 scatters; compared with the parallel CPU
+    re-indexer (itself pinned to the oracle) and with the sort-all path."""
+    rng = np.random.default_rng(2025)
+    n = 2**25 + 4099
+    vtx = rng.integers(0, 1 << 22, (n, 1), dtype=np.uint32).view(np.float32)
+    idx = rng.integers(0, n, (n - 12345, 1)).astype(np.int32)
+    _say("band marking only, N =", n)
+    got = _run(vtx, idx, HASH)
+    exp = oracle.reindex_parallel(vtx, idx, threads=16)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"), got, exp):
+        assert np.array_equal(g, e), label
+    other = _run(vtx, idx, SORT_ALL)
+    for g, o in zip(got, other):
+        assert np.array_equal(g, o)
