@@ -36,6 +36,7 @@ MRX_TUNING_WIDE_LOOKBACK = 1
 MRX_TUNING_CLAIMED_TILES = 2
 MRX_TUNING_SORT_ALL = 4
 MRX_TUNING_HASH_GROUPS = 8
+MRX_TUNING_BANDS = 16
 
 
 class Tuning(ctypes.Structure):

@@ -155,7 +155,7 @@ const SortVariant* pick_variant(int K, const mrx_tuning* t) {
   const auto& vs = variants_for(K);
   if (vs.empty()) return nullptr;
   constexpr int32_t known = MRX_TUNING_WIDE_LOOKBACK | MRX_TUNING_CLAIMED_TILES | MRX_TUNING_SORT_ALL |
-                             MRX_TUNING_HASH_GROUPS;
+                             MRX_TUNING_HASH_GROUPS | MRX_TUNING_BANDS;
   if (t && (t->flags & ~known) != 0) return nullptr;
   if (t && (t->flags & MRX_TUNING_SORT_ALL) && (t->flags & MRX_TUNING_HASH_GROUPS)) return nullptr;
   if (!t || (t->digit_bits == 0 && t->block_threads == 0 && t->items_per_thread == 0)) return &vs[0];
@@ -193,10 +193,13 @@ int hash_passes(int64_t n, const SortVariant& v) {
 // kMarkAndMap: the marking, old2new and the remap, with the index partition
 // in out_idx (its slots become the remapped tiles) and the new ids of the
 // entries in C. Chosen when there are enough entries to pay for the extra
-// launches, at most kMaxBands bands of at most 2^kMaxMarkShift (marking) or
-// 2^kMaxMapShift (map) vertices, and C holds m words.
+// launches (or MRX_TUNING_BANDS asks for it), at most kMaxBands bands of at
+// most 2^kMaxMarkShift (marking) or 2^kMaxMapShift (map) vertices, and C
+// holds m words. Below about 2^20 entries the five extra launches cost more
+// than the scattered accesses they replace (a 390K-entry soup: 0.28 against
+// 0.22 ms).
 enum BandMode { kBandNone = 0, kMarkOnly = 1, kMarkAndMap = 2 };
-constexpr int64_t kBandMinEntries = int64_t(1) << 16;
+constexpr int64_t kBandMinEntries = int64_t(1) << 20;
 struct BandPlan {
   int mode = kBandNone;
   int shift = 0, nb = 0;
@@ -206,9 +209,9 @@ struct BandPlan {
     return size_t(nb) * size_t(itiles) + size_t(itiles) + (mode == kMarkAndMap ? size_t(nb) * size_t(ptiles) : 0);
   }
 };
-BandPlan band_plan(int64_t n, int64_t m, int s) {
+BandPlan band_plan(int64_t n, int64_t m, int s, bool force) {
   BandPlan b;
-  if (n <= 0 || m < kBandMinEntries || m > n * int64_t(s)) return b;
+  if (n <= 0 || m <= 0 || (!force && m < kBandMinEntries) || m > n * int64_t(s)) return b;
   int want = kMinBandShift;  // about 256 bands where the band size allows it
   while (((n - 1) >> want) + 1 > 256) ++want;
   for (int mode : {int(kMarkAndMap), int(kMarkOnly)}) {
@@ -270,7 +273,6 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.scan_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_scan + 1));
   L.tiles_elem = (num_idx + kSelectTile - 1) / kSelectTile;
   L.elem_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_elem + 1));
-  L.used_v = off;   off = align_up(off + size_t(n));
   L.used_g = off;   off = align_up(off + size_t(n));
   if (L.P_hash) {
     L.hist_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash) * size_t(v.radix()));
@@ -278,12 +280,15 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
     L.dead_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash));
     L.group_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_group + 1));
   }
+  // last, so that a call whose Step 1 writes every flag (by bands) can leave
+  // it out of the clearing
+  L.used_v = off;   off = align_up(off + size_t(n));
   L.zero_end = off;
   L.buf_a = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   if (L.P_hash) {
     L.buf_c = off;  off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
-    L.band = band_plan(n, num_idx, L.S);
+    L.band = band_plan(n, num_idx, L.S, tuning && (tuning->flags & MRX_TUNING_BANDS));
     L.band_tab = off; off = align_up(off + sizeof(uint32_t) * L.band.words());
   }
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
@@ -454,14 +459,16 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
   auto next_counter = [&]() { return claimed ? counters + counter++ : nullptr; };
 
   if (!state_zeroed) {
+    // band marking writes every used flag: those need no clearing
+    const int64_t words = int64_t((L.band.mode != kBandNone ? L.used_v : L.zero_end) / 16);
     prof_mark("fill_zero", s);
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
-                       reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(ws), words, dev_status, out_num_vtx,
                        static_cast<int64_t*>(nullptr));
   }
-  // Step 1 and the hash-digit histograms: by vertex bands (partitioned
-  // entries and band table in C, which the grouping fills only later), else
-  // scattered byte stores beside the histograms
+  // Step 1 and the hash-digit histograms: Step 1 by vertex bands (the index
+  // partition in out_idx, or in C, which the grouping fills only later),
+  // else scattered byte stores beside the histograms
   const BandPlan& bp = L.band;
   const MarkArgs mark{idx, m, arity, n, nullptr, nullptr, 0, nullptr, live_elems, used_v, status};
   uint32_t* band_tab = reinterpret_cast<uint32_t*>(ws + L.band_tab);

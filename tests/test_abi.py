@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     lib = _lib.load()
-    assert lib.mrx_abi_version() == 4
+    assert lib.mrx_abi_version() == 5
     for code, name in [(0, "MRX_OK"), (1, "MRX_ERR_INVALID_ARGUMENT"), (2, "MRX_ERR_WORKSPACE_TOO_SMALL"),
                        (3, "MRX_ERR_INDEX_OUT_OF_RANGE"), (4, "MRX_ERR_TOO_LARGE"), (5, "MRX_ERR_HIP"),
                        (6, "MRX_ERR_UNSUPPORTED"), (7, "MRX_ERR_INTERNAL")]:
@@ -120,8 +120,8 @@ def _call(**kw):
     (dict(tuning=(7, 256, 16)), _lib.MRX_ERR_UNSUPPORTED),
     (dict(status=None), _lib.MRX_ERR_INVALID_ARGUMENT),              # the status word is required
     (dict(status=0x7F000102), _lib.MRX_ERR_INVALID_ARGUMENT),
-    (dict(tuning=(0, 0, 0, 16)), _lib.MRX_ERR_UNSUPPORTED),         # unknown flag bit
-    (dict(tuning=(8, 256, 16, 1 | 32)), _lib.MRX_ERR_UNSUPPORTED),
+    (dict(tuning=(0, 0, 0, 32)), _lib.MRX_ERR_UNSUPPORTED),         # unknown flag bit
+    (dict(tuning=(8, 256, 16, 1 | 64)), _lib.MRX_ERR_UNSUPPORTED),
     (dict(tuning=(0, 0, 0, 4 | 8)), _lib.MRX_ERR_UNSUPPORTED),      # sort-all and hash grouping at once
 ])
 def test_reindex_rejects_bad_arguments(kw, expected):
@@ -139,8 +139,8 @@ def test_tuning_flags():
         for fl in (_lib.MRX_TUNING_WIDE_LOOKBACK, _lib.MRX_TUNING_CLAIMED_TILES, both):
             st, need = _ws(5000, 12, 3000, tuning=(*t.as_tuple(), fl))
             assert st == 0, (t.as_tuple(), fl)
-    assert _ws(5000, 12, 3000, tuning=(0, 0, 0, 16))[0] == _lib.MRX_ERR_UNSUPPORTED
-    assert _ws(5000, 12, 3000, tuning=(0, 0, 0, both | 32))[0] == _lib.MRX_ERR_UNSUPPORTED
+    assert _ws(5000, 12, 3000, tuning=(0, 0, 0, 32))[0] == _lib.MRX_ERR_UNSUPPORTED
+    assert _ws(5000, 12, 3000, tuning=(0, 0, 0, both | 64))[0] == _lib.MRX_ERR_UNSUPPORTED
     sort_all, hashed = _lib.MRX_TUNING_SORT_ALL, _lib.MRX_TUNING_HASH_GROUPS
     assert _ws(5000, 12, 3000, tuning=(0, 0, 0, sort_all | hashed))[0] == _lib.MRX_ERR_UNSUPPORTED
     # the hash grouping needs a third element buffer; batches always sort all
@@ -148,6 +148,15 @@ def test_tuning_flags():
     st_h, need_h = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, hashed))
     st_d, need_d = _ws(100_000, 12, 90_000)
     assert st_s == st_h == st_d == 0 and need_h >= need_s + 100_000 * 16 and need_d == need_h
+    # vertex bands: band tables on top (hash path only, any size with the flag,
+    # from 2^20 index entries without it)
+    bands = _lib.MRX_TUNING_BANDS
+    st_b, need_b = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, hashed | bands))
+    assert st_b == 0 and need_b > need_h
+    assert _ws(100_000, 12, 90_000, tuning=(0, 0, 0, sort_all | bands)) == (0, need_s)
+    assert _ws(2_000_000, 12, 1_500_000)[1] == _ws(2_000_000, 12, 1_500_000, tuning=(0, 0, 0, bands))[1]
+    # more index entries than the element buffer holds: no bands
+    assert _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed | bands))[1] == _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed))[1]
     st_b, need_b = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, hashed))
     assert st_b == 0 and need_b < need_h
 
@@ -191,7 +200,7 @@ def test_merge_rejects_bad_arguments():
     assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no out_num_vtx
     bad = list(base); bad[16] = 256
     assert f(*bad) == _lib.MRX_ERR_WORKSPACE_TOO_SMALL
-    bad = list(base); bad[17] = _lib.make_tuning((0, 0, 0, 16))
+    bad = list(base); bad[17] = _lib.make_tuning((0, 0, 0, 32))
     assert f(*bad) == _lib.MRX_ERR_UNSUPPORTED
     bad = list(base); bad[14] = None
     assert f(*bad) == _lib.MRX_ERR_INVALID_ARGUMENT                              # no status word

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 HASH = 8       # MRX_TUNING_HASH_GROUPS
 SORT_ALL = 4   # MRX_TUNING_SORT_ALL
+BANDS = 16     # MRX_TUNING_BANDS: Steps 1 and 4 by vertex bands at any size
 
 
 def _say(*a):
@@ -188,8 +189,8 @@ def test_graph_replays_switch_between_grouping_and_fallback():
 
 
 def test_band_marking_shapes():
-    """Step 1 by vertex bands (at least 65,536 index entries on the hash
-    path): ragged vertex counts around the band-size steps, entries crowded
+    """Steps 1 and 4 by vertex bands (asked for at these sizes): ragged
+    vertex counts around the band-size steps, entries crowded
     into one band (slices longer than a wave), an index array that is only
     4-byte aligned, a vertex that is never referenced at each band edge."""
     rng = np.random.default_rng(77)
@@ -206,7 +207,7 @@ def test_band_marking_shapes():
         idx = idx.astype(np.int32)
         edges = np.arange(0, n, 4096)          # first vertex of each 4096-band: unused
         idx[np.isin(idx, edges)] = 1
-        check(vtx, idx.reshape(-1, 3), name)
+        check(vtx, idx.reshape(-1, 3), name, flags=HASH | BANDS)
     # index array at a 4-byte (not 16-byte) offset
     n, m = 150_000, 3 * 40_000
     vtx = rng.random((n, 3), dtype=np.float32)
@@ -215,7 +216,7 @@ def test_band_marking_shapes():
     assert idx_dev.data_ptr() % 16 != 0
     import paper_2109_09812_amd as mrx
     _say("unaligned index array")
-    r = mrx.reindex_mesh(torch.from_numpy(vtx.view(np.int32)).to(DEV), idx_dev, tuning=(0, 0, 0, HASH))
+    r = mrx.reindex_mesh(torch.from_numpy(vtx.view(np.int32)).to(DEV), idx_dev, tuning=(0, 0, 0, HASH | BANDS))
     exp = oracle.reindex(vtx, flat[1:].cpu().numpy().reshape(-1, 3))
     for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"),
                            (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(),
@@ -237,8 +238,8 @@ def test_band_marking_reports_bad_index(pos):
         _say("bad index", bad, "at", pos)
         with pytest.raises(IndexError):
             mrx.reindex_mesh(torch.from_numpy(vtx.view(np.int32)).to(DEV),
-                             torch.from_numpy(idx.reshape(-1, 3)).to(DEV), tuning=(0, 0, 0, HASH))
-    check(vtx, rng.integers(0, n, (70_000, 3)).astype(np.int32), "after the error")
+                             torch.from_numpy(idx.reshape(-1, 3)).to(DEV), tuning=(0, 0, 0, HASH | BANDS))
+    check(vtx, rng.integers(0, n, (70_000, 3)).astype(np.int32), "after the error", flags=HASH | BANDS)
 
 
 def test_band_map_in_place_and_unaligned_old2new():
@@ -253,7 +254,7 @@ def test_band_map_in_place_and_unaligned_old2new():
     _say("band map in place", m.vtx.shape[0])
     v = torch.from_numpy(m.vtx.view(np.int32)).to(DEV)
     i = torch.from_numpy(m.idx).to(DEV)
-    r = mrx.reindex_mesh(v, i.clone(), tuning=(0, 0, 0, HASH), in_place=True)
+    r = mrx.reindex_mesh(v, i.clone(), tuning=(0, 0, 0, HASH | BANDS), in_place=True)
     exp = oracle.reindex(m.vtx, m.idx)
     got = (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(), r.old2new.cpu().numpy(),
            r.new2old.cpu().numpy())
@@ -267,8 +268,8 @@ def test_band_map_in_place_and_unaligned_old2new():
     o2n_buf = torch.full((n + 4,), -7, dtype=torch.int32, device=DEV)
     n2o = torch.empty(n, dtype=torch.int32, device=DEV)
     meta = torch.zeros(2, dtype=torch.int64, device=DEV)
-    tun = _lib.make_tuning((0, 0, 0, HASH))
-    wsb = mrx.workspace_size(n, 4 * k, i.numel(), 1, (0, 0, 0, HASH))
+    tun = _lib.make_tuning((0, 0, 0, HASH | BANDS))
+    wsb = mrx.workspace_size(n, 4 * k, i.numel(), 1, (0, 0, 0, HASH | BANDS))
     ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
     o2n_ptr = o2n_buf.data_ptr() + 4
     assert o2n_ptr % 16 != 0
