@@ -101,7 +101,7 @@ def test_merge_all_tunings_and_flags():
     exp = oracle.merge(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
     tensors = _dev_batch(b)
     for t in mrx.tunings(12):
-        for fl in (0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES):
+        for fl in (0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES, mrx.MRX_TUNING_BANDS):
             _say("merge tuning", t.as_tuple(), fl)
             _same(_host(mrx.merge_meshes(*tensors, tuning=(*t.as_tuple(), fl))), exp, "merge tuning")
 
@@ -168,7 +168,8 @@ def test_extract_all_tunings_and_flags():
     keep = np.random.default_rng(8).random(m.idx.shape[0]) < 0.6
     exp = oracle.extract(m.vtx, m.idx, keep)
     for t in mrx.tunings(12):
-        for fl in (0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES):
+        for fl in (0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES, mrx.MRX_TUNING_BANDS,
+                   mrx.MRX_TUNING_BANDS | mrx.MRX_TUNING_CLAIMED_TILES):
             _say("extract tuning", t.as_tuple(), fl)
             _same(_extract(m.vtx, m.idx, keep, tuning=(*t.as_tuple(), fl)), exp, "extract tuning")
 

@@ -207,14 +207,16 @@ def test_single_digit_passes_are_skipped():
 
 
 def test_tuning_flags_match():
-    """64-bit look-back words (forced here; automatic from 2^30 vertices on)
-    and counter-claimed tiles give the same result as the defaults, in every
-    variant."""
+    """64-bit look-back words (forced here; automatic from 2^30 vertices on),
+    counter-claimed tiles and Steps 1 and 4 by vertex bands (forced here;
+    automatic from 2^20 index entries on) give the same result as the
+    defaults, in every variant."""
     import paper_2109_09812_amd as mrx
     m = meshgen.grid_soup(300, 0.07, 4321, "wide")
     exp = oracle.reindex(m.vtx, m.idx)
     flag_sets = (mrx.MRX_TUNING_WIDE_LOOKBACK, mrx.MRX_TUNING_CLAIMED_TILES,
-                 mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES)
+                 mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES,
+                 mrx.MRX_TUNING_BANDS | mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES)
     for t in mrx.tunings(12):
         for fl in flag_sets:
             shape = t.as_tuple()
