@@ -120,6 +120,7 @@ struct Control {
   int64_t num_groups;   // G: distinct values (per mesh, for a batch) among all vertices
   int64_t num_used;     // U of a batch (all meshes), or of the hash grouping
   int64_t sort_count;   // hash grouping: elements the key sort handles (U, or N after path = 1)
+  int64_t all_count;    // hash grouping: N after path = 1, else 0 (histogram of all N elements)
 };
 
 // Which kernels of a launch sequence run, decided on the device (the host

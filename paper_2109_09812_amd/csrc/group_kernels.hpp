@@ -13,6 +13,15 @@
 // elements are then sorted by their full key (Step 3's output order), a
 // fraction of the N the plain method sorts.
 //
+// A group is named by a position: each workgroup owns the buckets that start
+// in its chunk, i.e. a span of sorted positions disjoint from every other
+// chunk's, and its k-th group (in order of first copy) is called span start +
+// k, its k-th used group's element goes to slot span start + k of the
+// element buffer. Names stay below N and need no count of earlier chunks, so
+// the chunks never wait for each other; k_group_scan then adds up the per-chunk
+// counts, and k_group_compact_hist packs the used groups' elements densely
+// while counting their key digits.
+//
 // A bucket that does not fit the LDS window (many copies of one value, or an
 // unlucky hash) makes the call take the plain path instead: the same key
 // sort then runs on all N hash-ordered elements, followed by Section 2's
@@ -21,6 +30,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "sort_kernels.hpp"
 
 namespace mrx {
 
@@ -48,31 +58,17 @@ struct GroupShape {
   static_assert(TS * 3 >= WIN * 4, "table load");
 };
 
-// Look-back word of the grouping kernel (one per chunk, zeroed per call):
-// groups in bits 0..29, used groups in bits 30..59, bit 60 = some chunk up to
-// here met a bucket that did not fit, status in bits 62..63.
-struct GroupLb {
-  static __device__ __forceinline__ uint64_t pack(uint32_t st, uint32_t g, uint32_t u, uint32_t over) {
-    return (uint64_t(st) << 62) | (uint64_t(over & 1u) << 60) | (uint64_t(u & 0x3FFFFFFFu) << 30) |
-           uint64_t(g & 0x3FFFFFFFu);
-  }
-  static __device__ __forceinline__ uint32_t status(uint64_t w) { return uint32_t(w >> 62); }
-  static __device__ __forceinline__ uint32_t groups(uint64_t w) { return uint32_t(w) & 0x3FFFFFFFu; }
-  static __device__ __forceinline__ uint32_t used(uint64_t w) { return uint32_t(w >> 30) & 0x3FFFFFFFu; }
-  static __device__ __forceinline__ uint32_t over(uint64_t w) { return uint32_t(w >> 60) & 1u; }
-};
-
+// Per-chunk record of k_group: span start, used groups, groups, 1 if the
+// chunk's last bucket did not fit the window.
 struct GroupArgs {
   const uint32_t* elems;   // [n][K+1] elements in (hash bucket, id) order
   int64_t n;
   uint32_t bucket_mask;    // bucket of a record = hash & bucket_mask
-  uint2* pairs;            // [n] (group id, original id) per position
-  int32_t* rep;            // [G] smallest original id of each group
-  int32_t* cmap;           // [G] -1 for unused groups (used ones are set by the key sort's finalisation)
-  uint32_t* uelems;        // [U][K+1] (record, group id) of every used group, in group order
-  uint64_t* lookback;      // [chunks] zeroed
-  uint32_t* tile_counter;
-  Control* ctl;
+  uint2* pairs;            // [n] (group name, original id) per position
+  int32_t* rep;            // [n] smallest original id of each group, by name
+  int32_t* cmap;           // [n] -1 for unused groups (used ones are set by the key sort's finalisation)
+  uint32_t* uelems;        // [n][K+1] (record, group name) of every used group, in its span's slots
+  uint4* chunks;           // [chunks] (span start, used groups, groups, overflow)
   int32_t* status;
 };
 
@@ -97,8 +93,7 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
   __shared__ uint32_t s_keys[K * WIN];      // window records, word-major
   __shared__ uint32_t s_scratch[kScratch];  // buckets of the window, then the table
   __shared__ uint32_t s_cnt[2][IPT][WAVES];
-  __shared__ uint32_t s_tile, s_sq, s_eq;
-  __shared__ uint32_t s_gpre, s_upre;
+  __shared__ uint32_t s_sq, s_eq;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int64_t n = a.n;
@@ -106,7 +101,7 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
     s_sq = WIN;
     s_eq = WIN;
   }
-  const uint32_t tile = claim_tile(a.tile_counter, &s_tile);  // synchronises the block
+  const uint32_t tile = blockIdx.x;
   const int64_t c0 = int64_t(tile) * CHUNK;
   const int64_t c1 = min(n, c0 + CHUNK);
   const int qc1 = int(c1 - c0) + 1;  // window slot of position c1
@@ -232,73 +227,13 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
     if (h) s_scratch[slot[i]] = gb | (ub << 16);
   }
 
-  // ---- look-back across chunks: groups and used groups before this chunk.
-  // Wave 0 reads 64 predecessors' words per step (lane l: chunk hi - l), so a
-  // walk over chunks that have only published their own counts takes one
-  // round trip per 64 chunks.
-  if (wave == 0) {
-    const uint32_t g_own = active ? gt : 0u, u_own = active ? ut : 0u, o_own = over ? 1u : 0u;
-    uint64_t* lb = a.lookback + tile;
-    uint32_t gp = 0, up = 0, op = 0;
-    if (tile == 0) {
-      if (lane == 0) lb_store(lb, GroupLb::pack(kLbInclusive, g_own, u_own, o_own));
-    } else {
-      if (lane == 0) lb_store(lb, GroupLb::pack(kLbAggregate, g_own, u_own, o_own));
-      int64_t hi = int64_t(tile) - 1;
-      uint32_t spins = 0;
-      while (true) {
-        const int64_t t = hi - lane;
-        // below chunk 0: a virtual inclusive prefix of zero
-        const uint64_t w = t >= 0 ? lb_load(a.lookback + t) : GroupLb::pack(kLbInclusive, 0, 0, 0);
-        const uint32_t st = GroupLb::status(w);
-        const uint64_t incl = ballot(st == kLbInclusive);
-        const uint64_t none = ballot(st == 0);
-        // lanes up to and including the nearest inclusive prefix
-        const int stop = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
-        const uint64_t upto = stop == kWave - 1 ? ~uint64_t(0) : ((uint64_t(1) << (stop + 1)) - 1);
-        if (none & upto) {  // a predecessor that counts has not published yet
-          if (++spins >= kSpinLimit || flag_load(&a.ctl->abort)) {
-            if (lane == 0) {
-              __hip_atomic_store(&a.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
-            }
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        const bool mine = (upto >> lane) & 1u;
-        uint32_t g = mine ? GroupLb::groups(w) : 0u, u = mine ? GroupLb::used(w) : 0u;
-        uint32_t o = mine ? GroupLb::over(w) : 0u;
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-          g += __shfl_xor(g, off, kWave);
-          u += __shfl_xor(u, off, kWave);
-          o |= __shfl_xor(o, off, kWave);
-        }
-        gp += g;
-        up += u;
-        op |= o;
-        if (incl) break;
-        hi -= kWave;
-      }
-      if (lane == 0) lb_store(lb, GroupLb::pack(kLbInclusive, gp + g_own, up + u_own, op | o_own));
-    }
-    if (lane == 0) {
-      s_gpre = gp;
-      s_upre = up;
-      if (tile == gridDim.x - 1) {
-        const uint32_t any_over = op | o_own;
-        a.ctl->num_groups = int64_t(gp) + g_own;
-        a.ctl->num_used = int64_t(up) + u_own;
-        a.ctl->path = int32_t(any_over);
-        a.ctl->sort_count = any_over ? n : int64_t(up) + u_own;
-      }
-    }
-  }
-  __syncthreads();
+  // ---- the chunk's record; names start at the span's first position
+  const uint32_t span0 = owns ? uint32_t(c0 - 1 + sq) : 0u;
+  if (tid == 0)
+    a.chunks[tile] = make_uint4(span0, active ? ut : 0u, active ? gt : 0u, over ? 1u : 0u);
+  __syncthreads();  // the ranks the heads left in the table are read below
   if (!active) return;
-  const uint32_t gpre = s_gpre, upre = s_upre;
+  const uint32_t gpre = span0, upre = span0;
 
   // ---- outputs of the owned span
 #pragma unroll
@@ -333,14 +268,148 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
   }
 }
 
-// Plan of the key sort that follows the grouping: it reads buf[1] (the used
-// groups' elements) when the grouping succeeded, else buf[0] (all N
-// hash-ordered elements); passes whose digit is the same for every element
-// (dead, from the bucket scan) are skipped. One thread.
+// Totals of the grouping, one workgroup: used-group offsets of the chunks
+// (exclusive prefix, in chunk order), U, G, whether a bucket did not fit
+// (Control::path), and how many elements the key sort handles. Chunks are
+// taken kGroupScanSpan at a time: loaded into LDS with coalesced reads, each
+// thread adds up a contiguous run of them, a block scan joins the runs.
+constexpr int kGroupScanBlock = 1024;
+constexpr int kGroupScanPer = 16;
+constexpr int kGroupScanSpan = kGroupScanBlock * kGroupScanPer;
+
+static __global__ __launch_bounds__(kGroupScanBlock) void k_group_scan(const uint4* __restrict__ chunks,
+                                                                     int64_t tiles, int64_t n,
+                                                                     uint32_t* __restrict__ ubase, Control* ctl) {
+  __shared__ uint32_t s_u[kGroupScanSpan];
+  __shared__ uint32_t s_wave[kGroupScanBlock / kWave];
+  const int tid = threadIdx.x;
+  uint32_t carry = 0, groups = 0, over = 0;
+  for (int64_t b0 = 0; b0 < tiles; b0 += kGroupScanSpan) {
+    const int len = int(min(int64_t(kGroupScanSpan), tiles - b0));
+    for (int i = tid; i < len; i += kGroupScanBlock) {
+      const uint4 c = chunks[b0 + i];
+      s_u[i] = c.y;
+      groups += c.z;
+      over |= c.w;
+    }
+    __syncthreads();
+    uint32_t run[kGroupScanPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kGroupScanPer; ++j) {
+      const int i = tid * kGroupScanPer + j;
+      run[j] = sum;
+      sum += i < len ? s_u[i] : 0u;
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<kGroupScanBlock>(sum, s_wave, &total);  // synchronises
+#pragma unroll
+    for (int j = 0; j < kGroupScanPer; ++j) s_u[tid * kGroupScanPer + j] = carry + ex + run[j];
+    __syncthreads();
+    for (int i = tid; i < len; i += kGroupScanBlock) ubase[b0 + i] = s_u[i];
+    __syncthreads();  // s_u is refilled by the next round
+    carry += total;
+  }
+  // groups and the overflow flag over the block (group counts fit 32 bits:
+  // hash grouping runs below 2^30 vertices)
+  uint32_t gtotal;
+  (void)block_exclusive_scan<kGroupScanBlock>(groups, s_wave, &gtotal);
+  const int any = __syncthreads_or(over != 0u);
+  if (tid == 0) {
+    ctl->num_groups = int64_t(gtotal);
+    ctl->num_used = int64_t(carry);
+    ctl->path = any ? 1 : 0;
+    ctl->sort_count = any ? n : int64_t(carry);
+    ctl->all_count = any ? n : 0;
+  }
+}
+
+// Grouping path: packs the used groups' elements (slots span start + k of
+// each chunk) densely into `dense` at the chunk's used-group offset, and adds
+// every key digit of them to the LDS histograms (flushed once per
+// workgroup). A workgroup takes a run of consecutive chunks, whose elements
+// are one contiguous stretch of `dense`; each thread maps its dense positions
+// back to (chunk, slot) with a search over the run's offsets in LDS.
+struct GroupCompactArgs {
+  const uint32_t* sparse;  // [n][K+1]
+  const uint4* chunks;
+  const uint32_t* ubase;
+  int64_t tiles;
+  uint32_t* dense;         // [U][K+1]
+  uint32_t* hist;          // [P][2^D] global histograms
+  const Control* ctl;
+};
+
+constexpr int kCompactMaxChunks = 2048;  // chunks per workgroup (LDS of the run's offsets)
+
+template <int K, int D, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_group_compact_hist(GroupCompactArgs a) {
+  using DG = KeyDigits<K, D>;
+  constexpr int S = K + 1;
+  constexpr int P = DG::kPasses;
+  constexpr int WORDS = P << D;
+  // several items in flight per thread, but wide items one at a time: the
+  // multi-item register layout of items wider than 4 words is the one that
+  // miscounted histograms on the GPU (see items_per_group)
+  constexpr int UNROLL = S <= 4 ? 4 : 1;
+  __shared__ uint32_t s_h[WORDS];
+  __shared__ uint32_t s_base[kCompactMaxChunks + 1];
+  __shared__ uint32_t s_span[kCompactMaxChunks];
+  if (gate_closed(kGateGrouped, a.ctl)) return;
+  const int64_t t0 = int64_t(blockIdx.x) * a.tiles / gridDim.x;
+  const int64_t t1 = int64_t(blockIdx.x + 1) * a.tiles / gridDim.x;
+  const int nc = int(t1 - t0);  // <= kCompactMaxChunks (the launch sizes the grid so)
+  const uint32_t end = t1 < a.tiles ? a.ubase[t1] : uint32_t(a.ctl->num_used);
+  for (int i = threadIdx.x; i < nc; i += BLOCK) {
+    s_base[i] = a.ubase[t0 + i];
+    s_span[i] = a.chunks[t0 + i].x;
+  }
+  if (threadIdx.x == 0) s_base[nc] = end;
+  zero_histograms<WORDS, BLOCK>(s_h);  // synchronises
+  uint32_t last[P], run[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
+  const uint32_t first = nc > 0 ? s_base[0] : end;
+  const uint32_t total = end - first;
+  for (uint32_t j0 = 0; j0 < total; j0 += BLOCK * UNROLL) {
+    uint32_t e[UNROLL][S];
+    uint32_t pos[UNROLL];
+#pragma unroll
+    for (int r = 0; r < UNROLL; ++r) {
+      const uint32_t j = j0 + uint32_t(r * BLOCK + threadIdx.x);
+      pos[r] = first + j;
+      if (j < total) {
+        // chunk of dense position first + j: the last c with s_base[c] <= it
+        int lo = 0, hi = nc - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_base[mid] <= pos[r]) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t slot = s_span[lo] + (pos[r] - s_base[lo]);
+        load_words<S>(a.sparse + int64_t(slot) * S, e[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < UNROLL; ++r) {
+      if (j0 + uint32_t(r * BLOCK + threadIdx.x) >= total) continue;
+      store_words<S>(a.dense + int64_t(pos[r]) * S, e[r]);
+      hist_item<DG, D>(e[r], s_h, last, run);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    if (run[p]) atomicAdd(&s_h[p * (1 << D) + last[p]], run[p]);
+  flush_histograms<WORDS, BLOCK>(s_h, a.hist);
+}
+
+// Plan of the key sort that follows the grouping: it reads buf[0], which
+// holds the packed used groups' elements when the grouping succeeded, else
+// all N hash-ordered elements; passes whose digit is the same for every
+// element (dead, from the bucket scan) are skipped. One thread.
 static __global__ void k_group_sort_plan(SortBuffers b, const Control* ctl) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  (void)ctl;
   const uint32_t* dead = b.plan + b.passes + 1;
-  uint32_t in = ctl->path != 0 ? 0u : 1u;
+  uint32_t in = 0u;
   for (int p = 0; p < b.passes; ++p) {
     const bool skip = dead[p] != 0u;
     b.plan[p] = in | (skip ? 2u : 0u);

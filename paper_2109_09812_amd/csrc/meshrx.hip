@@ -234,7 +234,8 @@ struct Layout {
   int64_t tiles_sort = 0, tiles_scan = 0, tiles_group = 0;
   // zeroed region
   size_t ctl = 0, counters = 0, hist = 0, plan = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0,
-         used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_lookback = 0, zero_end = 0;
+         used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_chunks = 0, group_ubase = 0,
+         zero_end = 0;
   int64_t tiles_elem = 0;
   // scratch
   size_t buf_a = 0, buf_b = 0, buf_c = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, band_tab = 0,
@@ -278,7 +279,8 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
     L.hist_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash) * size_t(v.radix()));
     L.plan_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(2 * L.P_hash + 1));
     L.dead_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash));
-    L.group_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_group + 1));
+    L.group_chunks = off; off = align_up(off + sizeof(uint32_t) * 4 * size_t(L.tiles_group));
+    L.group_ubase = off; off = align_up(off + sizeof(uint32_t) * size_t(L.tiles_group));
   }
   // last, so that a call whose Step 1 writes every flag (by bands) can leave
   // it out of the clearing
@@ -442,7 +444,8 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
   uint32_t* dead_hash = reinterpret_cast<uint32_t*>(ws + L.dead_hash);
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
-  uint64_t* group_lookback = reinterpret_cast<uint64_t*>(ws + L.group_lookback);
+  uint4* group_chunks = reinterpret_cast<uint4*>(ws + L.group_chunks);
+  uint32_t* group_ubase = reinterpret_cast<uint32_t*>(ws + L.group_ubase);
   const bool wide = wide_lookback(n, tuning);
   const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
   uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
@@ -526,16 +529,21 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
     g.rep = rep;
     g.cmap = cmap;
     g.uelems = buf[2];
-    g.lookback = group_lookback;
-    g.tile_counter = next_counter();
-    g.ctl = ctl;
+    g.chunks = group_chunks;
     g.status = status;
     prof_mark("group", s);
     v.group(g, L.tiles_group, s);
+    prof_mark("group_scan", s);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kGroupScanBlock), 0, s,
+                       static_cast<const uint4*>(group_chunks), L.tiles_group, n, group_ubase, ctl);
 
-    // key sort: the used groups from C (or, on the fallback path, all of X)
+    // key sort of X: the used groups' elements packed from C (or, on the
+    // fallback path, all N hash-ordered elements)
     const SortBuffers sbk{{X, buf[2]}, plan, L.P_key};
-    const HistArgs ha{{buf[2], X}, &ctl->path, n, &ctl->sort_count, hist};
+    const GroupCompactArgs gc{buf[2], group_chunks, group_ubase, L.tiles_group, X, hist, ctl};
+    prof_mark("compact_histogram", s);
+    v.group_compact_hist(gc, s);
+    const HistArgs ha{{X, X}, nullptr, n, &ctl->all_count, hist};
     prof_mark("histogram", s);
     v.elem_hist(ha, s);
     prof_mark("scan_buckets", s);

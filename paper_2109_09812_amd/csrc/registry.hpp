@@ -75,6 +75,9 @@ struct SortVariant {
   void (*hash_hist)(const MarkArgs* mark, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
                     hipStream_t) = nullptr;
   void (*group)(const GroupArgs&, int64_t grid, hipStream_t) = nullptr;
+  // grouping path: dense copy of the used groups' elements + their key-digit
+  // histograms
+  void (*group_compact_hist)(const GroupCompactArgs&, hipStream_t) = nullptr;
   void (*finalize)(const FinalizeArgs&, int64_t grid, hipStream_t) = nullptr;
   int group_chunk = 0;           // sorted positions per grouping workgroup
   int group_target_bucket = 0;   // average bucket size the hash passes aim for
