@@ -69,8 +69,25 @@ struct GroupArgs {
   int32_t* cmap;           // [n] -1 for unused groups (used ones are set by the key sort's finalisation)
   uint32_t* uelems;        // [n][K+1] (record, group name) of every used group, in its span's slots
   uint4* chunks;           // [chunks] (span start, used groups, groups, overflow)
+  uint32_t* range_sums;    // [3][ranges] zeroed: used groups, groups and overflow of each run of
+                           // chunks k_group_compact_hist takes (spread over many addresses: atomics
+                           // on one address from every chunk would serialise)
+  int64_t ranges;          // that kernel's grid (group_compact_ranges)
   int32_t* status;
 };
+
+// Runs of consecutive chunks, one per workgroup of k_group_compact_hist: few
+// (each flushes its digit histograms once), each of at most kCompactMaxChunks.
+constexpr int kCompactMaxChunks = 2048;
+constexpr int64_t kCompactMinRanges = 512;
+__host__ __device__ inline int64_t group_compact_ranges(int64_t tiles) {
+  const int64_t by_size = (tiles + kCompactMaxChunks - 1) / kCompactMaxChunks;
+  return tiles < kCompactMinRanges ? tiles : (by_size > kCompactMinRanges ? by_size : kCompactMinRanges);
+}
+// First chunk of run w (of `ranges` runs over `tiles` chunks).
+__host__ __device__ inline int64_t group_range_start(int64_t w, int64_t tiles, int64_t ranges) {
+  return w * tiles / ranges;
+}
 
 template <int K>
 __device__ __forceinline__ bool lds_keys_equal(const uint32_t* s_keys, int a, int b, int win) {
@@ -227,10 +244,21 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
     if (h) s_scratch[slot[i]] = gb | (ub << 16);
   }
 
-  // ---- the chunk's record; names start at the span's first position
+  // ---- the chunk's record and its share of its run's sums; names start at
+  // the span's first position
   const uint32_t span0 = owns ? uint32_t(c0 - 1 + sq) : 0u;
-  if (tid == 0)
-    a.chunks[tile] = make_uint4(span0, active ? ut : 0u, active ? gt : 0u, over ? 1u : 0u);
+  if (tid == 0) {
+    const uint32_t u_own = active ? ut : 0u, g_own = active ? gt : 0u;
+    a.chunks[tile] = make_uint4(span0, u_own, g_own, over ? 1u : 0u);
+    // run of this chunk: the last w whose first chunk is at most `tile`
+    const int64_t T = int64_t(gridDim.x);
+    int64_t w = int64_t(tile) * a.ranges / T;
+    while (w + 1 < a.ranges && group_range_start(w + 1, T, a.ranges) <= tile) ++w;
+    while (w > 0 && group_range_start(w, T, a.ranges) > tile) --w;
+    if (u_own) atomicAdd(&a.range_sums[w], u_own);
+    if (g_own) atomicAdd(&a.range_sums[a.ranges + w], g_own);
+    if (over) atomicOr(&a.range_sums[2 * a.ranges + w], 1u);
+  }
   __syncthreads();  // the ranks the heads left in the table are read below
   if (!active) return;
   const uint32_t gpre = span0, upre = span0;
@@ -268,78 +296,25 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
   }
 }
 
-// Totals of the grouping, one workgroup: used-group offsets of the chunks
-// (exclusive prefix, in chunk order), U, G, whether a bucket did not fit
-// (Control::path), and how many elements the key sort handles. Chunks are
-// taken kGroupScanSpan at a time: loaded into LDS with coalesced reads, each
-// thread adds up a contiguous run of them, a block scan joins the runs.
-constexpr int kGroupScanBlock = 1024;
-constexpr int kGroupScanPer = 16;
-constexpr int kGroupScanSpan = kGroupScanBlock * kGroupScanPer;
-
-static __global__ __launch_bounds__(kGroupScanBlock) void k_group_scan(const uint4* __restrict__ chunks,
-                                                                     int64_t tiles, int64_t n,
-                                                                     uint32_t* __restrict__ ubase, Control* ctl) {
-  __shared__ uint32_t s_u[kGroupScanSpan];
-  __shared__ uint32_t s_wave[kGroupScanBlock / kWave];
-  const int tid = threadIdx.x;
-  uint32_t carry = 0, groups = 0, over = 0;
-  for (int64_t b0 = 0; b0 < tiles; b0 += kGroupScanSpan) {
-    const int len = int(min(int64_t(kGroupScanSpan), tiles - b0));
-    for (int i = tid; i < len; i += kGroupScanBlock) {
-      const uint4 c = chunks[b0 + i];
-      s_u[i] = c.y;
-      groups += c.z;
-      over |= c.w;
-    }
-    __syncthreads();
-    uint32_t run[kGroupScanPer], sum = 0;
-#pragma unroll
-    for (int j = 0; j < kGroupScanPer; ++j) {
-      const int i = tid * kGroupScanPer + j;
-      run[j] = sum;
-      sum += i < len ? s_u[i] : 0u;
-    }
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan<kGroupScanBlock>(sum, s_wave, &total);  // synchronises
-#pragma unroll
-    for (int j = 0; j < kGroupScanPer; ++j) s_u[tid * kGroupScanPer + j] = carry + ex + run[j];
-    __syncthreads();
-    for (int i = tid; i < len; i += kGroupScanBlock) ubase[b0 + i] = s_u[i];
-    __syncthreads();  // s_u is refilled by the next round
-    carry += total;
-  }
-  // groups and the overflow flag over the block (group counts fit 32 bits:
-  // hash grouping runs below 2^30 vertices)
-  uint32_t gtotal;
-  (void)block_exclusive_scan<kGroupScanBlock>(groups, s_wave, &gtotal);
-  const int any = __syncthreads_or(over != 0u);
-  if (tid == 0) {
-    ctl->num_groups = int64_t(gtotal);
-    ctl->num_used = int64_t(carry);
-    ctl->path = any ? 1 : 0;
-    ctl->sort_count = any ? n : int64_t(carry);
-    ctl->all_count = any ? n : 0;
-  }
-}
-
-// Grouping path: packs the used groups' elements (slots span start + k of
-// each chunk) densely into `dense` at the chunk's used-group offset, and adds
-// every key digit of them to the LDS histograms (flushed once per
-// workgroup). A workgroup takes a run of consecutive chunks, whose elements
+// Totals of the grouping (every workgroup adds up the runs' sums; workgroup 0
+// stores them: U, G, Control::path = some bucket did not fit, and the
+// element counts of the key sort). Then, on the grouping path, packs the used
+// groups' elements (slots span start + k of each chunk) densely into `dense`
+// at the chunk's used-group offset, and adds every key digit of them to the
+// LDS histograms (flushed once per workgroup). A workgroup takes a run of consecutive chunks, whose elements
 // are one contiguous stretch of `dense`; each thread maps its dense positions
 // back to (chunk, slot) with a search over the run's offsets in LDS.
 struct GroupCompactArgs {
-  const uint32_t* sparse;  // [n][K+1]
+  const uint32_t* sparse;     // [n][K+1]
   const uint4* chunks;
-  const uint32_t* ubase;
+  const uint32_t* range_sums; // [3][ranges] (k_group)
   int64_t tiles;
-  uint32_t* dense;         // [U][K+1]
-  uint32_t* hist;          // [P][2^D] global histograms
-  const Control* ctl;
+  int64_t ranges;             // the grid
+  int64_t n;
+  uint32_t* dense;            // [U][K+1]
+  uint32_t* hist;             // [P][2^D] global histograms
+  Control* ctl;               // totals of the grouping, set here by workgroup 0
 };
-
-constexpr int kCompactMaxChunks = 2048;  // chunks per workgroup (LDS of the run's offsets)
 
 template <int K, int D, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_group_compact_hist(GroupCompactArgs a) {
@@ -351,31 +326,71 @@ __global__ __launch_bounds__(BLOCK) void k_group_compact_hist(GroupCompactArgs a
   // multi-item register layout of items wider than 4 words is the one that
   // miscounted histograms on the GPU (see items_per_group)
   constexpr int UNROLL = S <= 4 ? 4 : 1;
+  constexpr int PER = kCompactMaxChunks / BLOCK;
   __shared__ uint32_t s_h[WORDS];
   __shared__ uint32_t s_base[kCompactMaxChunks + 1];
   __shared__ uint32_t s_span[kCompactMaxChunks];
-  if (gate_closed(kGateGrouped, a.ctl)) return;
-  const int64_t t0 = int64_t(blockIdx.x) * a.tiles / gridDim.x;
-  const int64_t t1 = int64_t(blockIdx.x + 1) * a.tiles / gridDim.x;
-  const int nc = int(t1 - t0);  // <= kCompactMaxChunks (the launch sizes the grid so)
-  const uint32_t end = t1 < a.tiles ? a.ubase[t1] : uint32_t(a.ctl->num_used);
-  for (int i = threadIdx.x; i < nc; i += BLOCK) {
-    s_base[i] = a.ubase[t0 + i];
-    s_span[i] = a.chunks[t0 + i].x;
+  __shared__ uint32_t s_wave[BLOCK / kWave];
+  const int tid = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  // totals, and the used groups of the runs before this one
+  uint32_t used = 0, before = 0, groups = 0, over = 0;
+  for (int64_t r = tid; r < a.ranges; r += BLOCK) {
+    const uint32_t ur = a.range_sums[r];
+    used += ur;
+    before += r < w ? ur : 0u;
+    groups += a.range_sums[a.ranges + r];
+    over |= a.range_sums[2 * a.ranges + r];
   }
-  if (threadIdx.x == 0) s_base[nc] = end;
+  uint32_t total_used, first, total_groups;
+  (void)block_exclusive_scan<BLOCK>(used, s_wave, &total_used);
+  (void)block_exclusive_scan<BLOCK>(before, s_wave, &first);
+  (void)block_exclusive_scan<BLOCK>(groups, s_wave, &total_groups);
+  const bool fallback = __syncthreads_or(over != 0u) != 0;
+  if (w == 0 && tid == 0) {
+    a.ctl->num_used = int64_t(total_used);
+    a.ctl->num_groups = int64_t(total_groups);
+    a.ctl->path = fallback ? 1 : 0;
+    a.ctl->sort_count = fallback ? a.n : int64_t(total_used);
+    a.ctl->all_count = fallback ? a.n : 0;
+  }
+  if (fallback) return;  // the same in every workgroup
+  const int64_t t0 = group_range_start(w, a.tiles, a.ranges);
+  const int64_t t1 = group_range_start(w + 1, a.tiles, a.ranges);
+  const int nc = int(t1 - t0);  // <= kCompactMaxChunks (group_compact_ranges)
+  // the run's chunks: offsets (exclusive prefix of their used counts) and span starts
+  uint32_t cnt[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = tid * PER + j;
+    uint4 c = make_uint4(0, 0, 0, 0);
+    if (i < nc) c = a.chunks[t0 + i];
+    cnt[j] = c.y;
+    sum += c.y;
+    if (i < nc) s_span[i] = c.x;
+  }
+  uint32_t run_total;
+  const uint32_t ex = block_exclusive_scan<BLOCK>(sum, s_wave, &run_total);
+  uint32_t acc = first + ex;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = tid * PER + j;
+    if (i < nc) s_base[i] = acc;
+    acc += cnt[j];
+  }
+  const uint32_t end = first + run_total;
+  if (tid == 0) s_base[nc] = end;
   zero_histograms<WORDS, BLOCK>(s_h);  // synchronises
   uint32_t last[P], run[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) { last[p] = 0; run[p] = 0; }
-  const uint32_t first = nc > 0 ? s_base[0] : end;
   const uint32_t total = end - first;
   for (uint32_t j0 = 0; j0 < total; j0 += BLOCK * UNROLL) {
     uint32_t e[UNROLL][S];
     uint32_t pos[UNROLL];
 #pragma unroll
     for (int r = 0; r < UNROLL; ++r) {
-      const uint32_t j = j0 + uint32_t(r * BLOCK + threadIdx.x);
+      const uint32_t j = j0 + uint32_t(r * BLOCK + tid);
       pos[r] = first + j;
       if (j < total) {
         // chunk of dense position first + j: the last c with s_base[c] <= it
@@ -390,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_compact_hist(GroupCompactArgs a
     }
 #pragma unroll
     for (int r = 0; r < UNROLL; ++r) {
-      if (j0 + uint32_t(r * BLOCK + threadIdx.x) >= total) continue;
+      if (j0 + uint32_t(r * BLOCK + tid) >= total) continue;
       store_words<S>(a.dense + int64_t(pos[r]) * S, e[r]);
       hist_item<DG, D>(e[r], s_h, last, run);
     }

@@ -234,7 +234,7 @@ struct Layout {
   int64_t tiles_sort = 0, tiles_scan = 0, tiles_group = 0;
   // zeroed region
   size_t ctl = 0, counters = 0, hist = 0, plan = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0,
-         used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_chunks = 0, group_ubase = 0,
+         used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_chunks = 0, group_ranges = 0,
          zero_end = 0;
   int64_t tiles_elem = 0;
   // scratch
@@ -280,7 +280,7 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
     L.plan_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(2 * L.P_hash + 1));
     L.dead_hash = off; off = align_up(off + sizeof(uint32_t) * size_t(L.P_hash));
     L.group_chunks = off; off = align_up(off + sizeof(uint32_t) * 4 * size_t(L.tiles_group));
-    L.group_ubase = off; off = align_up(off + sizeof(uint32_t) * size_t(L.tiles_group));
+    L.group_ranges = off; off = align_up(off + sizeof(uint32_t) * 3 * size_t(group_compact_ranges(L.tiles_group)));
   }
   // last, so that a call whose Step 1 writes every flag (by bands) can leave
   // it out of the clearing
@@ -445,7 +445,8 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
   uint64_t* lookback = reinterpret_cast<uint64_t*>(ws + L.lookback);
   uint64_t* scan_lookback = reinterpret_cast<uint64_t*>(ws + L.scan_lookback);
   uint4* group_chunks = reinterpret_cast<uint4*>(ws + L.group_chunks);
-  uint32_t* group_ubase = reinterpret_cast<uint32_t*>(ws + L.group_ubase);
+  uint32_t* group_range_sums = reinterpret_cast<uint32_t*>(ws + L.group_ranges);
+  const int64_t group_ranges = group_compact_ranges(L.tiles_group);
   const bool wide = wide_lookback(n, tuning);
   const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
   uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
@@ -530,17 +531,16 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
     g.cmap = cmap;
     g.uelems = buf[2];
     g.chunks = group_chunks;
+    g.range_sums = group_range_sums;
+    g.ranges = group_ranges;
     g.status = status;
     prof_mark("group", s);
     v.group(g, L.tiles_group, s);
-    prof_mark("group_scan", s);
-    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kGroupScanBlock), 0, s,
-                       static_cast<const uint4*>(group_chunks), L.tiles_group, n, group_ubase, ctl);
 
     // key sort of X: the used groups' elements packed from C (or, on the
     // fallback path, all N hash-ordered elements)
     const SortBuffers sbk{{X, buf[2]}, plan, L.P_key};
-    const GroupCompactArgs gc{buf[2], group_chunks, group_ubase, L.tiles_group, X, hist, ctl};
+    const GroupCompactArgs gc{buf[2], group_chunks, group_range_sums, L.tiles_group, group_ranges, n, X, hist, ctl};
     prof_mark("compact_histogram", s);
     v.group_compact_hist(gc, s);
     const HistArgs ha{{X, X}, nullptr, n, &ctl->all_count, hist};

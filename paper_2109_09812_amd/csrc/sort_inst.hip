@@ -113,11 +113,7 @@ void launch_hash_hist(const MarkArgs* ma, const uint32_t* vtx, int64_t n, int ph
 template <int D>
 void launch_group_compact_hist(const GroupCompactArgs& a, hipStream_t s) {
   constexpr int B = 256;
-  // few workgroups (each flushes its histograms once), each taking at most
-  // kCompactMaxChunks chunks
-  const int64_t grid = std::min<int64_t>(a.tiles, std::max<int64_t>(kElemHistGrid,
-                                                                   (a.tiles + kCompactMaxChunks - 1) / kCompactMaxChunks));
-  if (grid > 0) hipLaunchKernelGGL((k_group_compact_hist<K, D, B>), dim3(grid), dim3(B), 0, s, a);
+  if (a.ranges > 0) hipLaunchKernelGGL((k_group_compact_hist<K, D, B>), dim3(a.ranges), dim3(B), 0, s, a);
 }
 
 void launch_group(const GroupArgs& a, int64_t grid, hipStream_t s) {
