@@ -232,7 +232,10 @@ def bench_single(args, torch, mrx, meshgen):
             "band_partition": 8 * mi,
             "band_mark": 4 * mi + n,
             "hash_histogram": n * r_bytes,
-            "histogram": u * s_elem,
+            # the used values' elements packed from their span slots, with
+            # their key digits counted (the all-element histogram runs only
+            # after a bucket overflowed)
+            "compact_histogram": 2 * u * s_elem,
             "onesweep_hash_first": n * r_bytes + n + n * s_elem,
             "onesweep_hash": 2 * n * s_elem,
             "group": n * s_elem + 8 * n + 4 * g + 4 * (g - u) + u * s_elem,
