@@ -231,6 +231,7 @@ def bench_single(args, torch, mrx, meshgen):
             "mark_histogram": 5 * mi + n * r_bytes,
             "band_partition": 8 * mi,
             "band_mark": 4 * mi + n,
+            "band_mark_histogram": 4 * mi + n + n * r_bytes,
             "hash_histogram": n * r_bytes,
             # the used values' elements packed from their span slots, with
             # their key digits counted (the all-element histogram runs only

@@ -182,14 +182,13 @@ __device__ __forceinline__ void for_band_entries(const uint32_t* __restrict__ ro
   }
 }
 
+// One band of k_band_mark; s_bits holds (1 << shift) / 32 words of LDS.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_band_mark(BandArgs a) {
-  extern __shared__ uint32_t s_bits[];  // (1 << shift) / 32 words
+__device__ __forceinline__ void band_mark_body(const BandArgs& a, int64_t band, uint32_t* s_bits) {
   const int tid = threadIdx.x;
   const int words = (1 << a.shift) / 32;
   for (int w = tid; w < words; w += BLOCK) s_bits[w] = 0;
   __syncthreads();
-  const int64_t band = blockIdx.x;
   const int64_t lo = band << a.shift;
   const uint32_t mask = (1u << a.shift) - 1u;
   const uint32_t* part = a.part;
@@ -211,6 +210,12 @@ __global__ __launch_bounds__(BLOCK) void k_band_mark(BandArgs a) {
       for (int64_t t = q; t < hi; ++t) a.used[t] = uint8_t((w >> (t - q)) & 1u);
     }
   }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_band_mark(BandArgs a) {
+  extern __shared__ uint32_t s_bits[];
+  band_mark_body<BLOCK>(a, blockIdx.x, s_bits);
 }
 
 struct PairPartArgs {
@@ -378,13 +383,13 @@ static __global__ __launch_bounds__(kBandBlock) void k_band_remap(BandRemapArgs 
 }
 
 // Launches, each with the block shape its kernel is written for.
-inline void launch_band_partition(const BandArgs& a, hipStream_t s) {
+static inline void launch_band_partition(const BandArgs& a, hipStream_t s) {
   if (a.tiles > 0) hipLaunchKernelGGL(k_band_partition, dim3(a.tiles), dim3(kIdxPartBlock), 0, s, a);
 }
 
 // Small bands (Step 4 follows): many short workgroups; large bands: few,
 // each reading many entries.
-inline void launch_band_mark(const BandArgs& a, bool small_bands, hipStream_t s) {
+static inline void launch_band_mark(const BandArgs& a, bool small_bands, hipStream_t s) {
   const size_t bits_lds = (size_t(1) << a.shift) / 8;
   if (small_bands)
     hipLaunchKernelGGL(k_band_mark<256>, dim3(a.nb), dim3(256), bits_lds, s, a);
@@ -392,15 +397,15 @@ inline void launch_band_mark(const BandArgs& a, bool small_bands, hipStream_t s)
     hipLaunchKernelGGL(k_band_mark<1024>, dim3(a.nb), dim3(1024), bits_lds, s, a);
 }
 
-inline void launch_pair_partition(const PairPartArgs& a, hipStream_t s) {
+static inline void launch_pair_partition(const PairPartArgs& a, hipStream_t s) {
   if (a.tiles > 0) hipLaunchKernelGGL(k_pair_partition, dim3(a.tiles), dim3(kPairBlock), 0, s, a);
 }
 
-inline void launch_band_map(const BandMapArgs& a, int32_t nb, hipStream_t s) {
+static inline void launch_band_map(const BandMapArgs& a, int32_t nb, hipStream_t s) {
   hipLaunchKernelGGL(k_band_map, dim3(nb), dim3(kBandBlock), 0, s, a);
 }
 
-inline void launch_band_remap(const BandRemapArgs& a, int64_t tiles, hipStream_t s) {
+static inline void launch_band_remap(const BandRemapArgs& a, int64_t tiles, hipStream_t s) {
   if (tiles > 0) hipLaunchKernelGGL(k_band_remap, dim3(tiles), dim3(kBandBlock), 0, s, a);
 }
 

@@ -485,12 +485,19 @@ mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, i
                       bp.mode == kMarkAndMap ? 1 : 0, bp.itiles, ipart, itable, itile_valid, used_v, status};
     prof_mark("band_partition", s);
     launch_band_partition(ba, s);
-    prof_mark("band_mark", s);
-    launch_band_mark(ba, bp.mode == kMarkAndMap, s);
+    if (bp.mode == kMarkAndMap) {
+      prof_mark("band_mark_histogram", s);
+      v.band_mark_hash_hist(ba, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
+    } else {
+      prof_mark("band_mark", s);
+      launch_band_mark(ba, false, s);
+    }
   }
-  const bool fused_mark = m > 0 && bp.mode == kBandNone;
-  prof_mark(fused_mark ? "mark_histogram" : "hash_histogram", s);
-  v.hash_hist(fused_mark ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
+  if (bp.mode != kMarkAndMap) {
+    const bool fused_mark = m > 0 && bp.mode == kBandNone;
+    prof_mark(fused_mark ? "mark_histogram" : "hash_histogram", s);
+    v.hash_hist(fused_mark ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, ph, hist_hash, s);
+  }
   if (n > 0) {
     // stable sort by the hash digits; every hash pass runs (dead flags go to
     // a word nobody reads), so the elements end in X = buf[(ph - 1) & 1]

@@ -6,6 +6,7 @@
 
 #include <vector>
 
+#include "band_kernels.hpp"
 #include "group_kernels.hpp"
 #include "scan_kernels.hpp"
 #include "sort_kernels.hpp"
@@ -74,6 +75,10 @@ struct SortVariant {
   void (*elem_hist)(const HistArgs&, hipStream_t) = nullptr;
   void (*hash_hist)(const MarkArgs* mark, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
                     hipStream_t) = nullptr;
+  // Step 1's band marking (small bands, 256-thread blocks) in one launch
+  // with the hash-digit histograms
+  void (*band_mark_hash_hist)(const BandArgs& ba, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
+                              hipStream_t) = nullptr;
   void (*group)(const GroupArgs&, int64_t grid, hipStream_t) = nullptr;
   // grouping path: dense copy of the used groups' elements + their key-digit
   // histograms

@@ -100,6 +100,57 @@ void launch_hash_hist_ph(const MarkArgs* ma, const uint32_t* vtx, int64_t n, uin
   }
 }
 
+// Step 1's band marking (one block per band) and the hash-digit histograms
+// (hist_blocks blocks walking the record chunks) in one launch: the band
+// blocks wait on short slice reads, the histogram blocks stream records and
+// count in LDS, so spread evenly over the grid (block b is histogram block
+// h(b) = floor(b * H / (H + nb)) when h steps at b, else band b - h(b)) they
+// overlap on every CU.
+template <int D, int PH>
+__global__ __launch_bounds__(kRandBlock) void k_band_mark_hash_hist(BandArgs ba, HistArgs ha, int64_t hist_blocks) {
+  constexpr int B = kRandBlock, GROUPS = kHistGroups;
+  using DG = HashDigits<K, D, PH>;
+  constexpr int WORDS = PH << D;
+  constexpr int R = items_per_group(K);
+  __shared__ uint32_t s_h[WORDS];
+  extern __shared__ uint32_t s_bits[];
+  const int64_t total = hist_blocks + ba.nb;
+  const int64_t b = blockIdx.x;
+  const int64_t h0 = b * hist_blocks / total;
+  const int64_t h1 = (b + 1) * hist_blocks / total;
+  if (h1 > h0) {
+    const int64_t chunks = ((ha.n + R - 1) / R + B * GROUPS - 1) / (B * GROUPS);
+    if (h0 >= chunks) return;  // the whole block
+    zero_histograms<WORDS, B>(s_h);
+    for (int64_t c = h0; c < chunks; c += hist_blocks) histogram_chunk<DG, K, D, K, B, GROUPS>(ha.src[0], ha.n, s_h, c);
+    flush_histograms<WORDS, B>(s_h, ha.hist);
+  } else {
+    band_mark_body<B>(ba, b - h0, s_bits);
+  }
+}
+
+template <int D, int PH>
+void launch_band_mark_hash_hist_ph(const BandArgs& ba, const uint32_t* vtx, int64_t n, uint32_t* hist,
+                                   hipStream_t s) {
+  constexpr int B = kRandBlock, GROUPS = kHistGroups;
+  constexpr int R = items_per_group(K);
+  const int64_t per_block = int64_t(B) * GROUPS * R;
+  const int64_t hb = std::min((n + per_block - 1) / per_block, kElemHistGrid);
+  const HistArgs ha{{vtx, vtx}, nullptr, n, nullptr, hist};
+  const size_t bits_lds = (size_t(1) << ba.shift) / 8;
+  hipLaunchKernelGGL((k_band_mark_hash_hist<D, PH>), dim3(hb + ba.nb), dim3(B), bits_lds, s, ba, ha, hb);
+}
+
+template <int D>
+void launch_band_mark_hash_hist(const BandArgs& ba, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
+                                hipStream_t s) {
+  switch (ph) {
+    case 1: launch_band_mark_hash_hist_ph<D, 1>(ba, vtx, n, hist, s); break;
+    case 2: launch_band_mark_hash_hist_ph<D, 2>(ba, vtx, n, hist, s); break;
+    default: launch_band_mark_hash_hist_ph<D, 3>(ba, vtx, n, hist, s); break;
+  }
+}
+
 template <int D>
 void launch_hash_hist(const MarkArgs* ma, const uint32_t* vtx, int64_t n, int ph, uint32_t* hist,
                       hipStream_t s) {
@@ -196,6 +247,7 @@ SortVariant make() {
   v.flag_scan = &launch_flag_scan;
   v.elem_hist = &launch_elem_hist<D>;
   v.hash_hist = &launch_hash_hist<D>;
+  v.band_mark_hash_hist = &launch_band_mark_hash_hist<D>;
   v.group = &launch_group;
   v.group_compact_hist = &launch_group_compact_hist<D>;
   v.finalize = &launch_finalize;
