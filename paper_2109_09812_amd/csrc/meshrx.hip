@@ -412,19 +412,22 @@ mrx_status validate_single(const void* vtx, int64_t num_vtx, int32_t vtx_bytes, 
 }
 
 // The hash-grouping launch sequence of one mesh (see group_kernels.hpp):
-//   Step 1 (marking) with the hash-digit histograms; stable sort of
-//   (record, id | used << 31) by P_hash hash digits into X; grouping of each
-//   hash bucket in LDS (pairs (group, id) into Y, one (record, group)
-//   element per used group into C); key sort of those elements (or, if a
-//   bucket did not fit, of all N elements of X); then either the
-//   finalisation (output records, representatives, group -> new id) or, on
-//   the fallback path, Section 2's flag scan and compaction; the old2new
-//   scatter and the index remap (Step 4) are shared.
+//   Step 1 (marking, by vertex bands or by scattered stores) with the
+//   hash-digit histograms; stable sort of (record, id | used << 31) by
+//   P_hash hash digits into X; grouping of each hash bucket in LDS (pairs
+//   (group, id) into Y, one (record, group) element per used group into its
+//   chunk's slots of C); the totals and, on the grouping path, the used
+//   groups' elements packed into X with their key-digit histograms; key sort
+//   of X (the used groups, or, if a bucket did not fit, all N hash-ordered
+//   elements); then either the finalisation (output records,
+//   representatives, group -> new id) or, on the fallback path, Section 2's
+//   flag scan and compaction; Step 4 (old2new and the index remap, by
+//   vertex bands or by scattered accesses) is shared.
 // Buffers: A and B hold the hash passes (X = the last one written, Y = the
-// other), C the used groups (before the grouping: Step 1's index partition
-// when only the marking goes by bands); the key sort alternates between X
-// and C; by bands, Step 4 then partitions the pairs into X and puts the
-// index entries' new ids in C.
+// other), C the used groups' slots (before the grouping: Step 1's index
+// partition when only the marking goes by bands); the key sort alternates
+// between X and C starting from X; by bands, Step 4 then partitions the
+// pairs into X and puts the index entries' new ids in C.
 mrx_status launch_hash(const SortVariant& v, const Layout& L, const void* vtx, int64_t num_vtx,
                        int32_t vtx_bytes, const int32_t* idx, int64_t num_elems, int32_t arity,
                        const int64_t* live_elems, void* out_vtx, int32_t* out_idx, int32_t* old2new,
