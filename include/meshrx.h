@@ -101,15 +101,18 @@ typedef struct {
 #define MRX_TUNING_SORT_ALL 4
 #define MRX_TUNING_HASH_GROUPS 8
 
-/* On the hash-grouping path, the used marking (Section 2, Step 1) and, where
- * the vertex range splits into at most 1024 bands of 2^15 vertices, the
- * old2new map and the index remap (Step 4) go by vertex bands: the index
- * entries and the (group, vertex) pairs are first grouped per band, then each
- * band's part of the vertex-indexed tables is built in on-chip memory and
- * written out whole, instead of one scattered access per entry. The library
- * does so from 2^20 index entries on (where it is faster); this flag asks for
- * it at any size where it applies (it needs at most (K + 1) * num_vtx index
- * entries). The result is identical either way. */
+/* For single meshes (either strategy), the used marking (Section 2, Step 1)
+ * and, where the vertex range splits into at most 1024 bands of 2^15
+ * vertices, the old2new map and the index remap (Step 4) go by vertex bands:
+ * the index entries and the (group, vertex) pairs are first grouped per band,
+ * then each band's part of the vertex-indexed tables is built in on-chip
+ * memory and written out whole, instead of one scattered access per entry.
+ * The library does so with hash grouping from 2^20 index entries on (where
+ * index entries are scattered, as in soups, it is faster); this flag asks for
+ * it at any size and on the sort-all path too (where indices stored in order
+ * make the scattered accesses cheap), wherever it applies (at most
+ * (K + 1) * num_vtx index entries). Batched calls never do. The result is
+ * identical either way. */
 #define MRX_TUNING_BANDS 16
 
 /* Library ABI version (MRX_ABI_VERSION of the build). */

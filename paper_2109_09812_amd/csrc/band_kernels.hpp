@@ -218,6 +218,10 @@ __global__ __launch_bounds__(BLOCK) void k_band_mark(BandArgs a) {
   band_mark_body<BLOCK>(a, blockIdx.x, s_bits);
 }
 
+// Buffers of the sort-all path are decided on the device: with from_sort
+// set, the pairs are read from sort.spare() and the partition is written
+// into sort.sorted() (free once the flag scan has run) instead of the plain
+// pointers.
 struct PairPartArgs {
   const uint2* pairs;          // [n] (group, vertex) pairs of Step 3
   const int32_t* cmap;         // [G] new id of each group, negative if the group is unused
@@ -228,6 +232,8 @@ struct PairPartArgs {
   uint2* part;                 // [n] (new id or -1, vertex - band start)
   uint32_t* table;             // [nb][tiles]
   int32_t* status;
+  SortBuffers sort;
+  int32_t from_sort;
 };
 
 // The group ids of a tile of pairs are clustered (sorted, or grouped by
@@ -240,6 +246,8 @@ static __global__ __launch_bounds__(kPairBlock) void k_pair_partition(PairPartAr
   const int tid = threadIdx.x;
   for (int b = tid; b < kMaxBands; b += kPairBlock) s_cnt[b] = 0;
   __syncthreads();
+  const uint2* pairs = a.from_sort ? reinterpret_cast<const uint2*>(a.sort.spare()) : a.pairs;
+  uint2* out = a.from_sort ? reinterpret_cast<uint2*>(a.sort.sorted()) : a.part;
   const int64_t tile = blockIdx.x;
   const int64_t base = tile * kPairTile;
   // every load unconditional (clamped positions), so that all of them are
@@ -248,7 +256,7 @@ static __global__ __launch_bounds__(kPairBlock) void k_pair_partition(PairPartAr
   uint2 p[kPairItems];
 #pragma unroll
   for (int i = 0; i < kPairItems; ++i)
-    p[i] = stream_load(a.pairs + min(uint32_t(base + int64_t(i) * kPairBlock + tid), last));
+    p[i] = stream_load(pairs + min(uint32_t(base + int64_t(i) * kPairBlock + tid), last));
   int32_t val[kPairItems];
 #pragma unroll
   for (int i = 0; i < kPairItems; ++i) val[i] = a.cmap[min(p[i].x, last)];
@@ -289,7 +297,7 @@ static __global__ __launch_bounds__(kPairBlock) void k_pair_partition(PairPartAr
     if (vtx[i] != 0xFFFFFFFFu)
       s_stage[s_off[vtx[i] >> a.shift] + r[i]] = make_uint2(uint32_t(val[i] < 0 ? -1 : val[i]), vtx[i] & mask);
   __syncthreads();
-  for (uint32_t j = tid; j < valid; j += kPairBlock) stream_store(a.part + base + j, s_stage[j]);
+  for (uint32_t j = tid; j < valid; j += kPairBlock) stream_store(out + base + j, s_stage[j]);
 }
 
 struct BandMapArgs {
@@ -303,6 +311,8 @@ struct BandMapArgs {
   int32_t shift;               // <= kMaxMapShift
   int32_t* old2new;            // [n]
   int32_t* values;             // [m]: new id of the entry at the same place in ipart
+  SortBuffers sort;            // with from_sort: ppart = sort.sorted(), values = sort.spare()
+  int32_t from_sort;
 };
 
 static __global__ __launch_bounds__(kBandBlock) void k_band_map(BandMapArgs a) {
@@ -315,7 +325,7 @@ static __global__ __launch_bounds__(kBandBlock) void k_band_map(BandMapArgs a) {
   // vertices whose pair went missing (only after a failed wait) map to -1
   for (int i = tid; i < len; i += kBandBlock) s_map[i] = -1;
   __syncthreads();
-  const uint2* ppart = a.ppart;
+  const uint2* ppart = a.from_sort ? reinterpret_cast<const uint2*>(a.sort.sorted()) : a.ppart;
   for_band_entries<kBandBlock, 8>(
       a.ptable + size_t(band) * size_t(a.ptiles), a.ptiles, kPairTile,
       [&](uint32_t at) { return stream_load(ppart + at); },
@@ -335,7 +345,7 @@ static __global__ __launch_bounds__(kBandBlock) void k_band_map(BandMapArgs a) {
   }
   const uint32_t mask = (1u << a.shift) - 1u;
   const uint32_t* ipart = a.ipart;
-  int32_t* values = a.values;
+  int32_t* values = a.from_sort ? reinterpret_cast<int32_t*>(a.sort.spare()) : a.values;
   for_band_entries<kBandBlock, 8>(
       a.itable + size_t(band) * size_t(a.itiles), a.itiles, kBandTile,
       [&](uint32_t at) { return stream_load(ipart + at); },
@@ -350,6 +360,8 @@ struct BandRemapArgs {
   int32_t arity;
   const int64_t* live_elems;   // device, nullable
   int32_t* out_idx;            // [m]
+  SortBuffers sort;            // with from_sort: values = sort.spare()
+  int32_t from_sort;
 };
 
 // Entries dropped by the partition (out of range) come out as -1.
@@ -361,6 +373,7 @@ static __global__ __launch_bounds__(kBandBlock) void k_band_remap(BandRemapArgs 
   for (int j = tid; j < kBandTile; j += kBandBlock) s_out[j] = -1;
   __syncthreads();
   const uint32_t valid = a.tile_valid[tile];
+  const int32_t* values = a.from_sort ? reinterpret_cast<const int32_t*>(a.sort.spare()) : a.values;
   if (valid > 0) {
     // unconditional loads (clamped positions), all in flight at once
     constexpr int PER = kBandTile / kBandBlock;
@@ -370,7 +383,7 @@ static __global__ __launch_bounds__(kBandBlock) void k_band_remap(BandRemapArgs 
     for (int i = 0; i < PER; ++i) {
       const uint32_t j = min(uint32_t(i * kBandBlock + tid), valid - 1);
       e[i] = a.ipart[base + j];
-      x[i] = stream_load(a.values + base + j);
+      x[i] = stream_load(values + base + j);
     }
 #pragma unroll
     for (int i = 0; i < PER; ++i)

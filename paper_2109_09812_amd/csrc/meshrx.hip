@@ -188,12 +188,15 @@ int hash_passes(int64_t n, const SortVariant& v) {
   return std::max(1, std::min(3, (bits + v.D - 1) / v.D));
 }
 
-// Steps 1 and 4 by vertex bands (band_kernels.hpp) on the hash-grouping
-// path. kMarkOnly: the marking alone (the index partition in buffer C);
+// Steps 1 and 4 by vertex bands (band_kernels.hpp) for one mesh. kMarkOnly:
+// the marking alone (the index partition in a sort buffer that is free until
+// the marking is done: C on the hash-grouping path, B on the sort-all path);
 // kMarkAndMap: the marking, old2new and the remap, with the index partition
 // in out_idx (its slots become the remapped tiles) and the new ids of the
-// entries in C. Chosen when there are enough entries to pay for the extra
-// launches (or MRX_TUNING_BANDS asks for it), at most kMaxBands bands of at
+// entries in a free sort buffer (C, or the sort-all path's spare buffer once
+// the pairs in it are partitioned). Chosen when there are enough entries to pay for the extra
+// launches on the hash-grouping path (or MRX_TUNING_BANDS asks for it, on
+// either path), at most kMaxBands bands of at
 // most 2^kMaxMarkShift (marking) or 2^kMaxMapShift (map) vertices, and C
 // holds m words. Below about 2^20 entries the five extra launches cost more
 // than the scattered accesses they replace (a 390K-entry soup: 0.28 against
@@ -209,9 +212,9 @@ struct BandPlan {
     return size_t(nb) * size_t(itiles) + size_t(itiles) + (mode == kMarkAndMap ? size_t(nb) * size_t(ptiles) : 0);
   }
 };
-BandPlan band_plan(int64_t n, int64_t m, int s, bool force) {
+BandPlan band_plan(int64_t n, int64_t m, int s, bool force, bool automatic) {
   BandPlan b;
-  if (n <= 0 || m <= 0 || (!force && m < kBandMinEntries) || m > n * int64_t(s)) return b;
+  if (n <= 0 || m <= 0 || (!force && (!automatic || m < kBandMinEntries)) || m > n * int64_t(s)) return b;
   int want = kMinBandShift;  // about 256 bands where the band size allows it
   while (((n - 1) >> want) + 1 > 256) ++want;
   for (int mode : {int(kMarkAndMap), int(kMarkOnly)}) {
@@ -290,7 +293,13 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   if (L.P_hash) {
     L.buf_c = off;  off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
-    L.band = band_plan(n, num_idx, L.S, tuning && (tuning->flags & MRX_TUNING_BANDS));
+  }
+  if (nmesh == 1) {
+    // by default only with hash grouping, the strategy for meshes whose
+    // copies (and so index entries) are scattered; on the sort-all path,
+    // which the autotuner keeps for meshes stored in order (the paper's quad
+    // grid: 0.46 ms without bands, 0.75 ms with), only when asked for
+    L.band = band_plan(n, num_idx, L.S, tuning && (tuning->flags & MRX_TUNING_BANDS), L.P_hash > 0);
     L.band_tab = off; off = align_up(off + sizeof(uint32_t) * L.band.words());
   }
   L.uniq = off;     off = align_up(off + sizeof(uint32_t) * size_t(n) * K);
@@ -690,19 +699,36 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
   int32_t* status = dev_status;
 
+  const BandPlan& bp = L.band;
   // per-call state: look-back words, tile counters, histograms, flags, G
-  // (already cleared when a preceding step of the same call used it)
+  // (already cleared when a preceding step of the same call used it; band
+  // marking writes every used flag, so those need no clearing)
   if (!state_zeroed) {
+    const int64_t words = int64_t((bp.mode != kBandNone ? L.used_v : L.zero_end) / 16);
     prof_mark("fill_zero", s);
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
-                       reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status, out_num_vtx,
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(ws), words, dev_status, out_num_vtx,
                        static_cast<int64_t*>(nullptr));
   }
-  // Step 1: mark referenced vertices (and report out-of-range entries),
-  // with the digit histograms of Step 2 in the same launch where it applies
+  // Step 1: mark referenced vertices (and report out-of-range entries): by
+  // vertex bands (the index partition in out_idx, or in B, which the sort
+  // first writes in its second pass), else with the digit histograms of
+  // Step 2 in the same launch where it applies
   const MarkArgs mark{idx, m, arity, n, nullptr, nullptr, 0, nullptr, live_elems, used_v, status};
-  const bool fused = v.mark_hist_applies(n, m);
-  if (fused) {
+  uint32_t* band_tab = reinterpret_cast<uint32_t*>(ws + L.band_tab);
+  uint32_t* ipart = bp.mode == kMarkAndMap ? reinterpret_cast<uint32_t*>(out_idx) : buf[1];
+  uint32_t* itable = band_tab;
+  uint32_t* itile_valid = itable + size_t(bp.nb) * size_t(bp.itiles);
+  uint32_t* ptable = itile_valid + bp.itiles;
+  const bool fused = bp.mode == kBandNone && v.mark_hist_applies(n, m);
+  if (bp.mode != kBandNone) {
+    const BandArgs ba{idx, m, arity, n, live_elems, bp.shift, bp.nb, aligned(idx, 16) ? 1 : 0,
+                      bp.mode == kMarkAndMap ? 1 : 0, bp.itiles, ipart, itable, itile_valid, used_v, status};
+    prof_mark("band_partition", s);
+    launch_band_partition(ba, s);
+    prof_mark("band_mark", s);
+    launch_band_mark(ba, bp.mode == kMarkAndMap, s);
+  } else if (fused) {
     prof_mark("mark_histogram", s);
     v.mark_hist(mark, false, static_cast<const uint32_t*>(vtx), n, hist, s);
   } else if (m > 0) {
@@ -768,6 +794,48 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
     c.tag = uint32_t(L.P_key + 2);
     prof_mark("compact", s);
     hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
+    if (bp.mode == kMarkAndMap) {
+      // Step 4 by vertex bands: the pairs (in the spare buffer) partitioned
+      // into the sorted buffer, the index entries' new ids into the spare one
+      PairPartArgs pa{};
+      pa.cmap = cmap;
+      pa.n = n;
+      pa.shift = bp.shift;
+      pa.nb = bp.nb;
+      pa.tiles = bp.ptiles;
+      pa.table = ptable;
+      pa.status = status;
+      pa.sort = sb;
+      pa.from_sort = 1;
+      prof_mark("pair_partition", s);
+      launch_pair_partition(pa, s);
+      BandMapArgs ma{};
+      ma.ptable = ptable;
+      ma.ptiles = bp.ptiles;
+      ma.ipart = ipart;
+      ma.itable = itable;
+      ma.itiles = bp.itiles;
+      ma.n = n;
+      ma.shift = bp.shift;
+      ma.old2new = old2new;
+      ma.sort = sb;
+      ma.from_sort = 1;
+      prof_mark("band_map", s);
+      launch_band_map(ma, bp.nb, s);
+      BandRemapArgs ra{};
+      ra.ipart = ipart;
+      ra.tile_valid = itile_valid;
+      ra.m = m;
+      ra.arity = arity;
+      ra.live_elems = live_elems;
+      ra.out_idx = out_idx;
+      ra.sort = sb;
+      ra.from_sort = 1;
+      prof_mark("band_remap", s);
+      launch_band_remap(ra, bp.itiles, s);
+      prof_mark(nullptr, s);
+      return check_launch();
+    }
     prof_mark("old2new", s);
     hipLaunchKernelGGL((k_scatter_old2new<false>), dim3(rand_grid(n, kScatterItems)), dim3(kRandBlock), 0, s,
                        sb, static_cast<const uint2*>(nullptr), cmap, n, nullptr, nullptr, 0, nullptr, old2new);

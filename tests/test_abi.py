@@ -148,12 +148,17 @@ def test_tuning_flags():
     st_h, need_h = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, hashed))
     st_d, need_d = _ws(100_000, 12, 90_000)
     assert st_s == st_h == st_d == 0 and need_h >= need_s + 100_000 * 16 and need_d == need_h
-    # vertex bands: band tables on top (hash path only, any size with the flag,
-    # from 2^20 index entries without it)
+    # vertex bands: band tables on top (single meshes, any size and either
+    # strategy with the flag; without it only with hash grouping, from 2^20
+    # index entries)
     bands = _lib.MRX_TUNING_BANDS
     st_b, need_b = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, hashed | bands))
     assert st_b == 0 and need_b > need_h
-    assert _ws(100_000, 12, 90_000, tuning=(0, 0, 0, sort_all | bands)) == (0, need_s)
+    st_sb, need_sb = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, sort_all | bands))
+    assert st_sb == 0 and need_sb > need_s
+    assert _ws(100_000, 12, 90_000, 7, (0, 0, 0, bands)) == _ws(100_000, 12, 90_000, 7)   # batches: none
+    big = (2_000_000, 12, 1_500_000)
+    assert _ws(*big, tuning=(0, 0, 0, sort_all))[1] < _ws(*big, tuning=(0, 0, 0, sort_all | bands))[1]
     assert _ws(2_000_000, 12, 1_500_000)[1] == _ws(2_000_000, 12, 1_500_000, tuning=(0, 0, 0, bands))[1]
     # more index entries than the element buffer holds: no bands
     assert _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed | bands))[1] == _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed))[1]

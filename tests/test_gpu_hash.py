@@ -305,3 +305,48 @@ def test_band_marking_only_beyond_map_bands():
     other = _run(vtx, idx, SORT_ALL)
     for g, o in zip(got, other):
         assert np.array_equal(g, o)
+
+
+def test_sort_all_path_by_bands():
+    """Steps 1 and 4 by vertex bands on the sort-all path (asked for at these
+    sizes): the pairs come from the flag scan's spare buffer, the partitions
+    and new ids go into the sort buffers the plan leaves free; ragged band
+    and tile edges, in place, extraction and merging."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(31)
+    for n, m, name in ((70_000, 3 * 65_536, "sort-all bands, few vertices"),
+                       (1_048_577, 3 * 400_000, "sort-all bands, shift 13"),
+                       (262_144, 3 * 87_381 + 3, "sort-all bands, ragged last tile")):
+        vtx = rng.integers(0, 1 << 20, (n, 3), dtype=np.uint32).view(np.float32)
+        vtx[rng.integers(0, n, n // 3)] = vtx[rng.integers(0, n, n // 3)]
+        idx = rng.integers(0, n, m).astype(np.int32).reshape(-1, 3)
+        check(vtx, idx, name, flags=SORT_ALL | BANDS)
+    m = meshgen.grid_soup(300, 0.05, 77, "sa-inplace")
+    _say("sort-all bands in place")
+    r = mrx.reindex_mesh(torch.from_numpy(m.vtx.view(np.int32)).to(DEV), torch.from_numpy(m.idx).to(DEV),
+                         tuning=(0, 0, 0, SORT_ALL | BANDS), in_place=True)
+    exp = oracle.reindex(m.vtx, m.idx)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"),
+                           (r.out_vtx.cpu().numpy().view(np.uint32), r.out_idx.cpu().numpy(),
+                            r.old2new.cpu().numpy(), r.new2old.cpu().numpy()), exp):
+        assert np.array_equal(g, e), label
+    keep = rng.random(m.idx.shape[0]) < 0.4
+    _say("sort-all bands extract")
+    x = mrx.extract_submesh(torch.from_numpy(m.vtx.view(np.int32)).to(DEV), torch.from_numpy(m.idx).to(DEV),
+                            torch.from_numpy(keep).to(DEV), tuning=(0, 0, 0, SORT_ALL | BANDS))
+    ex = oracle.extract(m.vtx, m.idx, keep)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"),
+                           (x.out_vtx.cpu().numpy().view(np.uint32), x.out_idx.cpu().numpy(),
+                            x.old2new.cpu().numpy(), x.new2old.cpu().numpy()), ex):
+        assert np.array_equal(g, e), label
+    b = meshgen.batched(30, 100, 8000, 0.05, 4040)
+    _say("sort-all bands merge")
+    got = mrx.merge_meshes(torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)).to(DEV),
+                           torch.from_numpy(b.vtx_offsets).to(DEV),
+                           torch.from_numpy(np.ascontiguousarray(b.idx, dtype=np.int32)).to(DEV),
+                           torch.from_numpy(b.elem_offsets).to(DEV), tuning=(0, 0, 0, SORT_ALL | BANDS))
+    me = oracle.merge(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
+    for label, g, e in zip(("out_vtx", "out_idx", "old2new", "new2old"),
+                           (got.out_vtx.cpu().numpy().view(np.uint32), got.out_idx.cpu().numpy(),
+                            got.old2new.cpu().numpy(), got.new2old.cpu().numpy()), me):
+        assert np.array_equal(g, e), label
