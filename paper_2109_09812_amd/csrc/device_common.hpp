@@ -121,6 +121,7 @@ struct Control {
   int64_t num_used;     // U of a batch (all meshes), or of the hash grouping
   int64_t sort_count;   // hash grouping: elements the key sort handles (U, or N after path = 1)
   int64_t all_count;    // hash grouping: N after path = 1, else 0 (histogram of all N elements)
+  int64_t group_count;  // hash grouping of a batch: U while path = 0, else 0 (the (mesh, record) key sort)
 };
 
 // Which kernels of a launch sequence run, decided on the device (the host
@@ -159,6 +160,18 @@ __device__ __forceinline__ uint32_t hash_words(const uint32_t (&v)[N]) {
   h *= 0xc2b2ae35u;
   h ^= h >> 16;
   return h;
+}
+
+// Hash of a batch's record: the (K+1)-word record (mesh id, record words),
+// so that equal records of different meshes land in different buckets.
+template <int K, int N>
+__device__ __forceinline__ uint32_t hash_mesh_words(uint32_t mesh, const uint32_t (&v)[N]) {
+  static_assert(K <= N, "record words");
+  uint32_t x[K + 1];
+  x[0] = mesh;
+#pragma unroll
+  for (int w = 0; w < K; ++w) x[w + 1] = v[w];
+  return hash_words<K + 1>(x);
 }
 
 template <int K>

@@ -74,6 +74,12 @@ struct GroupArgs {
                            // on one address from every chunk would serialise)
   int64_t ranges;          // that kernel's grid (group_compact_ranges)
   int32_t* status;
+  // batches (k_group<K, true>): vertex offsets [nmesh+1] and their bucket
+  // table; the grouping key is then (mesh id, record) and uelems holds
+  // (mesh id, record, group name) elements of K+2 words
+  const int64_t* mesh_off;
+  const int32_t* mesh_tab;
+  int32_t nmesh;
 };
 
 // Runs of consecutive chunks, one per workgroup of k_group_compact_hist: few
@@ -97,17 +103,25 @@ __device__ __forceinline__ bool lds_keys_equal(const uint32_t* s_keys, int a, in
   return eq;
 }
 
-template <int K>
-__global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_SIMD) void k_group(GroupArgs a) {
-  using SH = GroupShape<K>;
-  constexpr int S = SH::S, BLOCK = SH::BLOCK, WIN = SH::WIN, CHUNK = SH::CHUNK, IPT = SH::IPT;
+// MESH (batches): the elements are (record, id) as always, but records are
+// told apart by (mesh of id, record): the key held in LDS, hashed and
+// compared is KW = K + 1 words with the mesh id first, and the shape is that
+// of KW-word records.
+template <int K, bool MESH>
+__global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
+                             GroupShape<MESH ? K + 1 : K>::MIN_WAVES_PER_SIMD) void k_group(GroupArgs a) {
+  constexpr int KW = MESH ? K + 1 : K;  // key words
+  using SH = GroupShape<KW>;
+  constexpr int S = K + 1;              // words of an input element
+  constexpr int SO = KW + 1;            // words of an output element
+  constexpr int BLOCK = SH::BLOCK, WIN = SH::WIN, CHUNK = SH::CHUNK, IPT = SH::IPT;
   constexpr int TS = SH::TS, TB = SH::TB;
   constexpr int WAVES = BLOCK / kWave;
   constexpr uint32_t kEmpty = 0xFFFFFFFFu;
   constexpr uint32_t kUsedBit = 0x80000000u;
   constexpr int kScratch = WIN > TS ? WIN : TS;
 
-  __shared__ uint32_t s_keys[K * WIN];      // window records, word-major
+  __shared__ uint32_t s_keys[KW * WIN];     // window keys, word-major
   __shared__ uint32_t s_scratch[kScratch];  // buckets of the window, then the table
   __shared__ uint32_t s_cnt[2][IPT][WAVES];
   __shared__ uint32_t s_sq, s_eq;
@@ -139,10 +153,19 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
 #pragma unroll
       for (int w = 0; w < S; ++w) e[w] = 0u;
     }
+    uint32_t key[KW];
+    if constexpr (MESH) {
+      key[0] = (pos >= 0 && pos < n) ? mesh_of(a.mesh_off, a.nmesh, int64_t(e[K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
 #pragma unroll
-    for (int w = 0; w < K; ++w) s_keys[w * WIN + q] = e[w];
+      for (int w = 0; w < K; ++w) key[w + 1] = e[w];
+    } else {
+#pragma unroll
+      for (int w = 0; w < K; ++w) key[w] = e[w];
+    }
+#pragma unroll
+    for (int w = 0; w < KW; ++w) s_keys[w * WIN + q] = key[w];
     ids[i] = e[K];
-    slot[i] = hash_words<K>(e);
+    slot[i] = hash_words<KW>(key);
     s_scratch[q] = slot[i] & a.bucket_mask;
   }
   __syncthreads();
@@ -185,7 +208,7 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
           break;
         }
       }
-      if (lds_keys_equal<K>(s_keys, int(cur & 0xFFFFu), q, WIN)) {
+      if (lds_keys_equal<KW>(s_keys, int(cur & 0xFFFFu), q, WIN)) {
         atomicMin(&s_scratch[sl], uint32_t(q));
         slot[i] = sl;
         break;
@@ -285,11 +308,11 @@ __global__ __launch_bounds__(GroupShape<K>::BLOCK, GroupShape<K>::MIN_WAVES_PER_
         atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
         continue;
       }
-      uint32_t e[S];
+      uint32_t e[SO];
 #pragma unroll
-      for (int w = 0; w < K; ++w) e[w] = s_keys[w * WIN + q];
-      e[K] = g;
-      store_words<S>(a.uelems + int64_t(u) * S, e);
+      for (int w = 0; w < KW; ++w) e[w] = s_keys[w * WIN + q];
+      e[KW] = g;
+      store_words<SO>(a.uelems + int64_t(u) * SO, e);
     } else {
       a.cmap[g] = -1;
     }
@@ -353,6 +376,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_compact_hist(GroupCompactArgs a
     a.ctl->path = fallback ? 1 : 0;
     a.ctl->sort_count = fallback ? a.n : int64_t(total_used);
     a.ctl->all_count = fallback ? a.n : 0;
+    a.ctl->group_count = fallback ? 0 : int64_t(total_used);
   }
   if (fallback) return;  // the same in every workgroup
   const int64_t t0 = group_range_start(w, a.tiles, a.ranges);
@@ -441,12 +465,15 @@ struct FinalizeArgs {
   SortBuffers bufs;        // sorted(): [U][K+1] (record, group id)
   const int32_t* rep;      // [G]
   int32_t* cmap;           // [G]
-  uint32_t* out_vtx;       // [U][K]
+  uint32_t* out_vtx;       // [U][K], or [U][K-1] with drop_first
   int32_t* new2old;        // [U], nullable
-  int64_t* out_num;
+  int64_t* out_num;        // nullable
   int64_t cap;             // n
   Control* ctl;
   int32_t* status;
+  // batches: the sorted keys are (mesh id, record); out_vtx takes the
+  // record words only
+  int32_t drop_first;
 };
 
 template <int K>
@@ -454,14 +481,17 @@ __global__ __launch_bounds__(256) void k_group_finalize(FinalizeArgs a) {
   constexpr int S = K + 1;
   if (gate_closed(kGateGrouped, a.ctl)) return;
   const int64_t u = a.ctl->num_used;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.out_num = u;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.out_num) *a.out_num = u;
   const uint32_t* sorted = a.bufs.sorted();
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int drop = a.drop_first ? 1 : 0;
+  const int64_t ko = K - drop;  // words of an output record
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < u && c < a.cap; c += stride) {
     uint32_t e[S];
     load_words<S>(sorted + c * S, e);
 #pragma unroll
-    for (int w = 0; w < K; ++w) a.out_vtx[c * K + w] = e[w];
+    for (int w = 0; w < K; ++w)
+      if (w >= drop) a.out_vtx[c * ko + (w - drop)] = e[w];
     const uint32_t g = e[K];
     if (int64_t(g) >= a.cap) {
       atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);

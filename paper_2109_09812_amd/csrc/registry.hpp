@@ -86,6 +86,14 @@ struct SortVariant {
   void (*finalize)(const FinalizeArgs&, int64_t grid, hipStream_t) = nullptr;
   int group_chunk = 0;           // sorted positions per grouping workgroup
   int group_target_bucket = 0;   // average bucket size the hash passes aim for
+  // hash grouping of a batch: hash-digit histograms of (mesh id, record),
+  // and the grouping by (mesh id, record) whose used elements (K + 2 words)
+  // the K + 1 build sorts (null for K = 16)
+  void (*hash_mesh_hist)(const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh, const int32_t* tab,
+                         int ph, uint32_t* hist, hipStream_t) = nullptr;
+  void (*group_mesh)(const GroupArgs&, int64_t grid, hipStream_t) = nullptr;
+  int group_mesh_chunk = 0;
+  int group_mesh_target_bucket = 0;
 
   int tile() const { return block * ipt; }
   int radix() const { return 1 << D; }

@@ -32,6 +32,13 @@ void launch_pass_w(const SortPassArgs& a, int mode, int64_t grid, hipStream_t s)
     case kPassHash:
       hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassHash, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
+    case kPassFirstHashMesh:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassFirstHashMesh, WIDE>), dim3(grid), dim3(BLOCK), 0, s,
+                         a);
+      break;
+    case kPassHashMesh:
+      hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassHashMesh, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
+      break;
     default:
       hipLaunchKernelGGL((k_onesweep<K, D, BLOCK, IPT, kPassMesh, WIDE>), dim3(grid), dim3(BLOCK), 0, s, a);
       break;
@@ -161,6 +168,29 @@ void launch_hash_hist(const MarkArgs* ma, const uint32_t* vtx, int64_t n, int ph
   }
 }
 
+// Hash-digit histograms of a batch's records (hash of (mesh id, record)),
+// on a capped grid of workgroups that each walk several chunks.
+template <int D, int PH>
+void launch_hash_mesh_hist_ph(const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh, const int32_t* tab,
+                              uint32_t* hist, hipStream_t s) {
+  constexpr int B = 256, GROUPS = kHistGroups;
+  const int64_t per_block = int64_t(B) * GROUPS;
+  const int64_t grid = std::min((n + per_block - 1) / per_block, kElemHistGrid);
+  if (grid > 0)
+    hipLaunchKernelGGL((k_hash_mesh_histogram<K, D, PH, B, GROUPS>), dim3(grid), dim3(B), 0, s, vtx, n, off, nmesh,
+                       tab, hist);
+}
+
+template <int D>
+void launch_hash_mesh_hist(const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh, const int32_t* tab,
+                           int ph, uint32_t* hist, hipStream_t s) {
+  switch (ph) {
+    case 1: launch_hash_mesh_hist_ph<D, 1>(vtx, n, off, nmesh, tab, hist, s); break;
+    case 2: launch_hash_mesh_hist_ph<D, 2>(vtx, n, off, nmesh, tab, hist, s); break;
+    default: launch_hash_mesh_hist_ph<D, 3>(vtx, n, off, nmesh, tab, hist, s); break;
+  }
+}
+
 template <int D>
 void launch_group_compact_hist(const GroupCompactArgs& a, hipStream_t s) {
   constexpr int B = 256;
@@ -168,8 +198,16 @@ void launch_group_compact_hist(const GroupCompactArgs& a, hipStream_t s) {
 }
 
 void launch_group(const GroupArgs& a, int64_t grid, hipStream_t s) {
-  if (grid > 0) hipLaunchKernelGGL((k_group<K>), dim3(grid), dim3(GroupShape<K>::BLOCK), 0, s, a);
+  if (grid > 0) hipLaunchKernelGGL((k_group<K, false>), dim3(grid), dim3(GroupShape<K>::BLOCK), 0, s, a);
 }
+
+// Grouping by (mesh id, record) for a batch; its elements go on to the sort
+// of K + 1 key words (the K + 1 build), so the widest records have none.
+#if MRX_INST_K < 16
+void launch_group_mesh(const GroupArgs& a, int64_t grid, hipStream_t s) {
+  if (grid > 0) hipLaunchKernelGGL((k_group<K, true>), dim3(grid), dim3(GroupShape<K + 1>::BLOCK), 0, s, a);
+}
+#endif
 
 void launch_finalize(const FinalizeArgs& a, int64_t grid, hipStream_t s) {
   if (grid > 0) hipLaunchKernelGGL((k_group_finalize<K>), dim3(grid), dim3(256), 0, s, a);
@@ -253,6 +291,12 @@ SortVariant make() {
   v.finalize = &launch_finalize;
   v.group_chunk = GroupShape<K>::CHUNK;
   v.group_target_bucket = GroupShape<K>::TARGET_BUCKET;
+  v.hash_mesh_hist = &launch_hash_mesh_hist<D>;
+#if MRX_INST_K < 16
+  v.group_mesh = &launch_group_mesh;
+  v.group_mesh_chunk = GroupShape<K + 1>::CHUNK;
+  v.group_mesh_target_bucket = GroupShape<K + 1>::TARGET_BUCKET;
+#endif
   return v;
 }
 

@@ -20,6 +20,8 @@ enum PassMode : int {
   kPassMesh = 2,       // element to element, digit from the element's mesh id (batches)
   kPassFirstHash = 3,  // as kPassFirst, digit from the record's hash (hash grouping)
   kPassHash = 4,       // as kPassKey, digit from the record's hash
+  kPassFirstHashMesh = 5,  // as kPassFirstHash, hash of (mesh id, record) (hash grouping of a batch)
+  kPassHashMesh = 6,       // as kPassHash, hash of (mesh id, record)
 };
 
 struct SortPassArgs {
@@ -36,7 +38,7 @@ struct SortPassArgs {
   uint32_t* tile_counter;
   Control* ctl;
   int32_t* status;
-  const int64_t* mesh_off;      // mesh passes: [nmesh+1] vertex offsets
+  const int64_t* mesh_off;      // mesh and mesh-hash passes: [nmesh+1] vertex offsets
   const int32_t* mesh_tab;      // mesh passes: bucket table of mesh_off (mesh_of)
   const int64_t* n_dev;         // non-null: the element count is min(n, *n_dev), read on the device
   int32_t nmesh;
@@ -232,6 +234,40 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(HistArgs a) {
   flush_histograms<WORDS, BLOCK>(s_h, a.hist);
 }
 
+// Hash-digit histograms of a batch's records for the PH hash passes of its
+// hash grouping: record i is hashed together with its mesh id (the mesh
+// whose vertex range holds i), as the hash passes and the grouping do.
+template <int K, int D, int PH, int BLOCK, int GROUPS>
+__global__ __launch_bounds__(BLOCK) void k_hash_mesh_histogram(const uint32_t* __restrict__ vtx, int64_t n,
+                                                               const int64_t* __restrict__ off, int32_t nmesh,
+                                                               const int32_t* __restrict__ tab,
+                                                               uint32_t* __restrict__ hist) {
+  using DG = HashDigits<K + 1, D, PH>;
+  constexpr int WORDS = PH << D;
+  __shared__ uint32_t s_h[WORDS];
+  const int64_t chunks = (n + BLOCK * GROUPS - 1) / (BLOCK * GROUPS);
+  if (int64_t(blockIdx.x) >= chunks) return;  // whole block
+  zero_histograms<WORDS, BLOCK>(s_h);
+  uint32_t last[PH], run[PH];
+#pragma unroll
+  for (int p = 0; p < PH; ++p) { last[p] = 0; run[p] = 0; }
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    for (int it = 0; it < GROUPS; ++it) {
+      const int64_t i = c * (BLOCK * GROUPS) + int64_t(it) * BLOCK + threadIdx.x;
+      if (i >= n) break;
+      uint32_t x[K + 1];
+      x[0] = mesh_of(off, nmesh, i, tab);
+#pragma unroll
+      for (int w = 0; w < K; ++w) x[w + 1] = vtx[i * K + w];
+      hist_item<DG, D>(x, s_h, last, run);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PH; ++p)
+    if (run[p]) atomicAdd(&s_h[p * (1 << D) + last[p]], run[p]);
+  flush_histograms<WORDS, BLOCK>(s_h, hist);
+}
+
 // Histograms of the mesh-id passes of a batch: mesh b contributes its vertex
 // count to digit (b >> shift_q) of mesh pass q.
 template <int D>
@@ -318,8 +354,9 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   // Key passes recompute each element's digit from its reordered words;
   // mesh and hash passes (whose digit costs a lookup or a hash) stage it in
   // LDS.
-  constexpr bool kFirst = MODE == kPassFirst || MODE == kPassFirstHash;
-  constexpr bool kHash = MODE == kPassFirstHash || MODE == kPassHash;
+  constexpr bool kFirst = MODE == kPassFirst || MODE == kPassFirstHash || MODE == kPassFirstHashMesh;
+  constexpr bool kMeshHash = MODE == kPassFirstHashMesh || MODE == kPassHashMesh;
+  constexpr bool kHash = MODE == kPassFirstHash || MODE == kPassHash || kMeshHash;
   constexpr bool kStageDigits = MODE == kPassMesh || kHash;
   __shared__ uint16_t s_dig[kStageDigits ? TILE : 1];
   __shared__ uint32_t s_wave[WAVES];
@@ -428,7 +465,11 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
       dig[j] = (m >> a.shift) & MASK;
     } else {
-      if constexpr (kHash)
+      if constexpr (kMeshHash) {
+        const int64_t pos = wave_base + j * kWave;
+        const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
+        dig[j] = (hash_mesh_words<K>(m, v[j]) >> a.shift) & MASK;
+      } else if constexpr (kHash)
         dig[j] = (hash_words<K>(v[j]) >> a.shift) & MASK;
       else
         dig[j] = masked_digit<D, K>(v[j], lo_mask, hi_mask, a.shift);

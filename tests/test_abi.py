@@ -143,7 +143,7 @@ def test_tuning_flags():
     assert _ws(5000, 12, 3000, tuning=(0, 0, 0, both | 64))[0] == _lib.MRX_ERR_UNSUPPORTED
     sort_all, hashed = _lib.MRX_TUNING_SORT_ALL, _lib.MRX_TUNING_HASH_GROUPS
     assert _ws(5000, 12, 3000, tuning=(0, 0, 0, sort_all | hashed))[0] == _lib.MRX_ERR_UNSUPPORTED
-    # the hash grouping needs a third element buffer; batches always sort all
+    # the hash grouping needs a third element buffer
     st_s, need_s = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, sort_all))
     st_h, need_h = _ws(100_000, 12, 90_000, tuning=(0, 0, 0, hashed))
     st_d, need_d = _ws(100_000, 12, 90_000)
@@ -162,8 +162,14 @@ def test_tuning_flags():
     assert _ws(2_000_000, 12, 1_500_000)[1] == _ws(2_000_000, 12, 1_500_000, tuning=(0, 0, 0, bands))[1]
     # more index entries than the element buffer holds: no bands
     assert _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed | bands))[1] == _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed))[1]
+    # batches: hash grouping by (mesh id, record) keeps three buffers of
+    # K + 2-word elements; sort-all two of K + 1 words; 16-word records have
+    # no hash grouping in a batch
     st_b, need_b = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, hashed))
-    assert st_b == 0 and need_b < need_h
+    st_bs, need_bs = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, sort_all))
+    assert st_b == st_bs == 0 and need_b >= need_bs + 100_000 * 20 and need_b > need_h
+    assert _ws(100_000, 12, 90_000, 2) == (0, need_bs)   # not the default for batches
+    assert _ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, hashed)) == _ws(100_000, 64, 90_000, 2)
 
 
 def test_workspace_one_byte_short():

@@ -1,0 +1,185 @@
+"""GPU parity of the batched re-index with hash grouping (vertices told apart
+by (mesh id, record)): every mesh must equal the per-mesh oracle, equal
+vertices of different meshes must never merge, and a bucket too large for
+the on-chip window must make the device finish by sorting everything."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+HASH = 8  # MRX_TUNING_HASH_GROUPS
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(b: meshgen.Batch):
+    return (torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)).to(DEV),
+            torch.from_numpy(b.vtx_offsets).to(DEV),
+            torch.from_numpy(b.idx).to(DEV),
+            torch.from_numpy(b.elem_offsets).to(DEV))
+
+
+def check_batch(b: meshgen.Batch, res):
+    ov, ooff, oi, o2n, n2o = oracle.reindex_batched(b.vtx, b.idx, b.vtx_offsets, b.elem_offsets)
+    assert np.array_equal(res.out_vtx_offsets.cpu().numpy(), ooff)
+    assert np.array_equal(res.out_vtx.cpu().numpy().view(np.uint32), ov.view(np.uint32))
+    assert np.array_equal(res.out_idx.cpu().numpy(), oi)
+    assert np.array_equal(res.old2new.cpu().numpy(), o2n)
+    assert np.array_equal(res.new2old.cpu().numpy(), n2o)
+    if b.expected_unique is not None:
+        assert np.array_equal(np.diff(ooff), b.expected_unique)
+
+
+def pooled_batch(sizes, words, seed, pool_frac=0.3, arity=3, unused_frac=0.05):
+    """Meshes of K-word random records drawn from one shared pool (so equal
+    records occur inside a mesh and across meshes), with random indices
+    that leave about `unused_frac` of each mesh's vertices unreferenced."""
+    rng = np.random.default_rng(seed)
+    n = int(sum(sizes))
+    pool = rng.integers(0, 2**32, size=(max(1, int(pool_frac * n)), words), dtype=np.uint64).astype(np.uint32)
+    vtx = pool[rng.integers(0, pool.shape[0], n)]
+    vo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    parts, eo = [], [0]
+    for sz in sizes:
+        live = max(1, int(sz * (1 - unused_frac)))
+        e = (live // arity) if sz else 0
+        parts.append(rng.integers(0, max(live, 1), size=(e, arity)).astype(np.int32))
+        eo.append(eo[-1] + e)
+    return meshgen.Batch(vtx, np.concatenate(parts), vo, np.array(eo, np.int64), None, f"pool{words}")
+
+
+@pytest.mark.parametrize("meshes,hi,seed", [(2, 3000, 1), (7, 30_000, 2), (64, 20_000, 3), (300, 5_000, 4)])
+def test_batched_hash_matches_per_mesh_oracle(meshes, hi, seed):
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(meshes, 100, hi, 0.05, 1900 + seed)
+    _say("hash batch", meshes, "meshes", b.vtx.shape[0], "vertices")
+    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH)))
+
+
+@pytest.mark.parametrize("fl", [1, 2, 3])
+def test_batched_hash_lookback_flags(fl):
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(120, 100, 20_000, 0.05, 2616)
+    _say("hash batch flags", fl)
+    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH | fl)))
+
+
+@pytest.mark.parametrize("words", [1, 2, 4, 5, 8, 15, 16])
+def test_batched_hash_record_widths(words):
+    """Every record width; 16-word records have no (mesh, record) sort of
+    17 words and run the sort-all path instead (same result)."""
+    import paper_2109_09812_amd as mrx
+    sizes = [5000, 1, 0, 23_001, 777, 9000, 40_000, 2]
+    b = pooled_batch(sizes, words, 70 + words)
+    _say("hash batch width", words, b.vtx.shape[0], "vertices")
+    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH)))
+
+
+def test_batched_hash_every_tuning():
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(50, 100, 6000, 0.05, 2515)
+    tensors = to_dev(b)
+    for t in mrx.tunings(12):
+        tt = t.as_tuple()
+        _say("hash batch tuning", tt)
+        check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=(*tt[:3], HASH)))
+
+
+def test_batched_hash_cross_mesh_never_merge():
+    import paper_2109_09812_amd as mrx
+    m = meshgen.batched(1, 500, 501, 0.05, 31).mesh(0)
+    vtx = np.concatenate([m.vtx] * 3)
+    idx = np.concatenate([m.idx] * 3)
+    n, e = m.num_vtx, m.idx.shape[0]
+    b = meshgen.Batch(vtx, idx, np.arange(4, dtype=np.int64) * n, np.arange(4, dtype=np.int64) * e,
+                      np.full(3, m.expected_unique), "triplicate")
+    _say("hash triplicate batch")
+    res = mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH))
+    check_batch(b, res)
+    assert int(res.out_vtx_offsets[-1]) == 3 * m.expected_unique
+
+
+def test_batched_hash_empty_meshes():
+    import paper_2109_09812_amd as mrx
+    parts = [meshgen.batched(1, 200, 201, 0.05, 40 + s).mesh(0) for s in range(3)]
+    empty_v = np.zeros((0, 3), np.float32)
+    empty_i = np.zeros((0, 3), np.int32)
+    vs = [empty_v, parts[0].vtx, empty_v, parts[1].vtx, empty_v, parts[2].vtx, empty_v]
+    is_ = [empty_i, parts[0].idx, empty_i, empty_i, empty_i, parts[2].idx, empty_i]
+    vo = np.concatenate([[0], np.cumsum([v.shape[0] for v in vs])]).astype(np.int64)
+    eo = np.concatenate([[0], np.cumsum([i.shape[0] for i in is_])]).astype(np.int64)
+    exp = np.array([0, parts[0].expected_unique, 0, 0, 0, parts[2].expected_unique, 0])
+    b = meshgen.Batch(np.concatenate(vs), np.concatenate(is_), vo, eo, exp, "holes")
+    _say("hash batch with empty meshes")
+    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH)))
+
+
+def test_batched_hash_index_out_of_range():
+    import paper_2109_09812_amd as mrx
+    b = meshgen.batched(5, 100, 1000, 0.05, 61)
+    idx = b.idx.copy()
+    m2 = int(b.elem_offsets[2])
+    idx[m2, 0] = int(b.vtx_offsets[3] - b.vtx_offsets[2])
+    bb = meshgen.Batch(b.vtx, idx, b.vtx_offsets, b.elem_offsets, b.expected_unique, "bad")
+    _say("hash batch out of range")
+    with pytest.raises(IndexError):
+        mrx.reindex_mesh_batched(*to_dev(bb), tuning=(0, 0, 0, HASH))
+
+
+def overflow_batch(seed=5):
+    """A batch where one mesh holds 6,000 copies of one value: its hash
+    bucket cannot fit the grouping window, so the call sorts everything."""
+    b = meshgen.batched(12, 100, 4000, 0.05, seed)
+    big = meshgen.batched(1, 3000, 3001, 0.0, seed + 1).mesh(0)
+    # mesh 3 replaced by a soup whose 6,000 first vertices are one value
+    bv = big.vtx.copy()
+    bv[:6000] = bv[0]
+    sizes = np.diff(b.vtx_offsets).copy()
+    esz = np.diff(b.elem_offsets).copy()
+    sizes[3], esz[3] = bv.shape[0], big.idx.shape[0]
+    vs = [b.vtx[b.vtx_offsets[i]:b.vtx_offsets[i + 1]] if i != 3 else bv for i in range(12)]
+    is_ = [b.idx[b.elem_offsets[i]:b.elem_offsets[i + 1]] if i != 3 else big.idx for i in range(12)]
+    vo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eo = np.concatenate([[0], np.cumsum(esz)]).astype(np.int64)
+    return meshgen.Batch(np.concatenate(vs), np.concatenate(is_), vo, eo, None, "overflow")
+
+
+def test_batched_hash_bucket_overflow_sorts_everything():
+    import paper_2109_09812_amd as mrx
+    b = overflow_batch()
+    _say("hash batch with an overflowing bucket", b.vtx.shape[0], "vertices")
+    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH)))
+
+
+def test_batched_hash_graph_switches_paths():
+    """One captured graph, contents alternating between a batch the grouping
+    handles and one whose bucket overflows (same shapes): the device picks
+    the path in every replay."""
+    import paper_2109_09812_amd as mrx
+    over = overflow_batch(9)
+    rng = np.random.default_rng(3)
+    vtx = over.vtx.copy()
+    # same shapes, no overflow: jitter every vertex of mesh 3 to a distinct value
+    v0, v1 = int(over.vtx_offsets[3]), int(over.vtx_offsets[4])
+    vtx[v0:v1] = rng.random((v1 - v0, 3), dtype=np.float32)
+    fine = meshgen.Batch(vtx, over.idx, over.vtx_offsets, over.elem_offsets, None, "fine")
+    tensors = to_dev(over)
+    _say("hash batch: capture graph")
+    gr = mrx.GraphedBatchedReindexer(*tensors, tuning=(0, 0, 0, HASH))
+    for rep, b in enumerate([fine, over, fine, over]):
+        _say("hash batch replay", rep, b.name)
+        tensors[0].copy_(torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)))
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        check_batch(b, gr.result())
+        _ = (tensors[0].float() * 2).sum().item()
