@@ -642,7 +642,7 @@ def batched_kernels_only(args, torch, mrx, meshgen):
     vo = torch.from_numpy(b.vtx_offsets).to(dev)
     idx = torch.from_numpy(b.idx).to(dev)
     eo = torch.from_numpy(b.elem_offsets).to(dev)
-    tuning = args.tuning or (8, 256, 16, 0)
+    tuning = args.tuning or (8, 256, 16, 8)
     r = mrx.BatchedReindexer(vtx, vo, idx, eo, tuning=tuning)
     torch.cuda.synchronize()
     for _ in range(args.warmup + args.steps):

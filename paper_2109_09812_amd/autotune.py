@@ -1,6 +1,7 @@
 """Autotuner for the radix-sort kernel shape (digit width, workgroup size,
-items per thread) and, for single meshes, the way duplicates are found
-(sort all vertices by their full record, or hash grouping).
+items per thread) and the way duplicates are found (sort all vertices by
+their full record, or hash grouping; for a batch the key is (mesh id,
+record) either way).
 
 Every compiled variant and either strategy compute the identical result, so
 tuning is purely a speed choice. Which strategy wins depends on the data (how
@@ -27,7 +28,7 @@ import torch
 from . import _lib
 from .api import BatchedReindexer, Reindexer
 
-SCHEMA = 2
+SCHEMA = 3
 
 
 def cache_path() -> str:
@@ -77,8 +78,8 @@ _STRATEGY_FLAGS = (_lib.MRX_TUNING_SORT_ALL, _lib.MRX_TUNING_HASH_GROUPS)
 
 def candidates(vtx_bytes: int, num_vtx: int, batched: bool):
     """Every compiled kernel shape, with each strategy a call of this shape
-    can take (batches and meshes of 2^30 or more vertices always sort all)."""
-    flags = (0,) if batched or num_vtx >= (1 << 30) else _STRATEGY_FLAGS
+    can take (meshes and batches of 2^30 or more vertices always sort all)."""
+    flags = (0,) if num_vtx >= (1 << 30) else _STRATEGY_FLAGS
     out = []
     for t in _lib.tunings(vtx_bytes):
         for fl in flags:

@@ -121,7 +121,6 @@ struct Control {
   int64_t num_used;     // U of a batch (all meshes), or of the hash grouping
   int64_t sort_count;   // hash grouping: elements the key sort handles (U, or N after path = 1)
   int64_t all_count;    // hash grouping: N after path = 1, else 0 (histogram of all N elements)
-  int64_t group_count;  // hash grouping of a batch: U while path = 0, else 0 (the (mesh, record) key sort)
 };
 
 // Which kernels of a launch sequence run, decided on the device (the host
@@ -172,6 +171,15 @@ __device__ __forceinline__ uint32_t hash_mesh_words(uint32_t mesh, const uint32_
 #pragma unroll
   for (int w = 0; w < K; ++w) x[w + 1] = v[w];
   return hash_words<K + 1>(x);
+}
+
+// Hash bucket of a batch's record: every mesh owns a contiguous range of
+// buckets, mb[mesh] = (first bucket, bucket count - 1) with a power-of-two
+// count sized to the mesh, so that the hash-ordered elements stay grouped by
+// mesh (and the vertex ids of neighbouring elements close together).
+__device__ __forceinline__ uint32_t mesh_bucket(const uint2* __restrict__ mb, uint32_t mesh, uint32_t h) {
+  const uint2 e = mb[mesh];
+  return e.x + (h & e.y);
 }
 
 template <int K>

@@ -75,10 +75,10 @@ struct GroupArgs {
   int64_t ranges;          // that kernel's grid (group_compact_ranges)
   int32_t* status;
   // batches (k_group<K, true>): vertex offsets [nmesh+1] and their bucket
-  // table; the grouping key is then (mesh id, record) and uelems holds
-  // (mesh id, record, group name) elements of K+2 words
+  // table; the grouping key is then (mesh id, record)
   const int64_t* mesh_off;
   const int32_t* mesh_tab;
+  const uint2* mesh_buckets;  // each mesh's hash buckets (mesh_bucket)
   int32_t nmesh;
 };
 
@@ -106,14 +106,17 @@ __device__ __forceinline__ bool lds_keys_equal(const uint32_t* s_keys, int a, in
 // MESH (batches): the elements are (record, id) as always, but records are
 // told apart by (mesh of id, record): the key held in LDS, hashed and
 // compared is KW = K + 1 words with the mesh id first, and the shape is that
-// of KW-word records.
+// of KW-word records. Each mesh's vertices then occupy its own vertex range
+// of sorted positions (its buckets come after those of the meshes before
+// it), and a group is named by the sorted position of its first copy, which
+// lies in that range: the mesh of a group is the mesh of its name.
 template <int K, bool MESH>
 __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
                              GroupShape<MESH ? K + 1 : K>::MIN_WAVES_PER_SIMD) void k_group(GroupArgs a) {
   constexpr int KW = MESH ? K + 1 : K;  // key words
   using SH = GroupShape<KW>;
   constexpr int S = K + 1;              // words of an input element
-  constexpr int SO = KW + 1;            // words of an output element
+  constexpr int KO = MESH ? 1 : 0;      // first record word of a key
   constexpr int BLOCK = SH::BLOCK, WIN = SH::WIN, CHUNK = SH::CHUNK, IPT = SH::IPT;
   constexpr int TS = SH::TS, TB = SH::TB;
   constexpr int WAVES = BLOCK / kWave;
@@ -166,7 +169,10 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
     for (int w = 0; w < KW; ++w) s_keys[w * WIN + q] = key[w];
     ids[i] = e[K];
     slot[i] = hash_words<KW>(key);
-    s_scratch[q] = slot[i] & a.bucket_mask;
+    if constexpr (MESH)
+      s_scratch[q] = mesh_bucket(a.mesh_buckets, key[0], slot[i]);
+    else
+      s_scratch[q] = slot[i] & a.bucket_mask;
   }
   __syncthreads();
 
@@ -262,9 +268,11 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
     const uint64_t um = ballot((uheadm >> i) & 1u);
     gb += uint32_t(popc64(hm & lanemask_lt()));
     ub += uint32_t(popc64(um & lanemask_lt()));
-    // heads leave their group's rank (low half) and used rank (high half)
-    // in the table for the other copies; both are below WIN <= 2^16
-    if (h) s_scratch[slot[i]] = gb | (ub << 16);
+    // heads leave their group's rank (batches: their window slot) in the low
+    // half and their used rank in the high half of the table entry for the
+    // other copies; both are below WIN <= 2^16
+    const uint32_t q = uint32_t(i * BLOCK + tid);
+    if (h) s_scratch[slot[i]] = (MESH ? q : gb) | (ub << 16);
   }
 
   // ---- the chunk's record and its share of its run's sums; names start at
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
     const int q = i * BLOCK + tid;
     const int64_t pos = c0 - 1 + q;
     const uint32_t ranks = s_scratch[slot[i]];
-    const uint32_t g = gpre + (ranks & 0xFFFFu);
+    const uint32_t g = MESH ? uint32_t(c0 - 1) + (ranks & 0xFFFFu) : gpre + (ranks & 0xFFFFu);
     const uint32_t org = ids[i] & 0x7FFFFFFFu;
     if (int64_t(g) >= n || pos < 0 || pos >= n) {  // only after a failed wait
       atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
@@ -308,11 +316,11 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
         atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);
         continue;
       }
-      uint32_t e[SO];
+      uint32_t e[S];
 #pragma unroll
-      for (int w = 0; w < KW; ++w) e[w] = s_keys[w * WIN + q];
-      e[KW] = g;
-      store_words<SO>(a.uelems + int64_t(u) * SO, e);
+      for (int w = 0; w < K; ++w) e[w] = s_keys[(w + KO) * WIN + q];
+      e[K] = g;
+      store_words<S>(a.uelems + int64_t(u) * S, e);
     } else {
       a.cmap[g] = -1;
     }
@@ -376,7 +384,6 @@ __global__ __launch_bounds__(BLOCK) void k_group_compact_hist(GroupCompactArgs a
     a.ctl->path = fallback ? 1 : 0;
     a.ctl->sort_count = fallback ? a.n : int64_t(total_used);
     a.ctl->all_count = fallback ? a.n : 0;
-    a.ctl->group_count = fallback ? 0 : int64_t(total_used);
   }
   if (fallback) return;  // the same in every workgroup
   const int64_t t0 = group_range_start(w, a.tiles, a.ranges);
@@ -465,15 +472,12 @@ struct FinalizeArgs {
   SortBuffers bufs;        // sorted(): [U][K+1] (record, group id)
   const int32_t* rep;      // [G]
   int32_t* cmap;           // [G]
-  uint32_t* out_vtx;       // [U][K], or [U][K-1] with drop_first
+  uint32_t* out_vtx;       // [U][K]
   int32_t* new2old;        // [U], nullable
   int64_t* out_num;        // nullable
   int64_t cap;             // n
   Control* ctl;
   int32_t* status;
-  // batches: the sorted keys are (mesh id, record); out_vtx takes the
-  // record words only
-  int32_t drop_first;
 };
 
 template <int K>
@@ -484,14 +488,11 @@ __global__ __launch_bounds__(256) void k_group_finalize(FinalizeArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.out_num) *a.out_num = u;
   const uint32_t* sorted = a.bufs.sorted();
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  const int drop = a.drop_first ? 1 : 0;
-  const int64_t ko = K - drop;  // words of an output record
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < u && c < a.cap; c += stride) {
     uint32_t e[S];
     load_words<S>(sorted + c * S, e);
 #pragma unroll
-    for (int w = 0; w < K; ++w)
-      if (w >= drop) a.out_vtx[c * ko + (w - drop)] = e[w];
+    for (int w = 0; w < K; ++w) a.out_vtx[c * K + w] = e[w];
     const uint32_t g = e[K];
     if (int64_t(g) >= a.cap) {
       atomicMax(a.status, 7 /* MRX_ERR_INTERNAL */);

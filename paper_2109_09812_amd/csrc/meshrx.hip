@@ -53,23 +53,51 @@ __global__ void k_batch_offsets(const int64_t* __restrict__ vtx_off, int32_t nme
   out_off[b] = r;
 }
 
-// Output offsets of a batch after its hash grouping: the used values are
-// sorted by (mesh id, record) with the mesh id in word 0 of each
-// `stride`-word element, so mesh b's outputs start at the first sorted
-// position whose mesh id is at least b (a binary search per mesh).
-__global__ void k_batch_offsets_sorted(SortBuffers bufs, int32_t stride, const Control* ctl, int32_t nmesh,
-                                       int64_t* __restrict__ out_off) {
+// Output offsets of a batch after its hash grouping: the used groups'
+// elements (record, name), packed densely before the key sort, are in order
+// of their names, the sorted positions of the groups' first copies, which
+// lie in their mesh's vertex range; so mesh b's outputs start at the number
+// of packed elements whose name is below vtx_off[b] (a binary search per
+// mesh). The key sort by (mesh id, record) keeps the meshes in that order.
+__global__ void k_batch_offsets_dense(const uint32_t* __restrict__ dense, int32_t stride, const Control* ctl,
+                                      const int64_t* __restrict__ vtx_off, int32_t nmesh,
+                                      int64_t* __restrict__ out_off) {
   if (gate_closed(kGateGrouped, ctl)) return;
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nmesh) return;
   const int64_t u = ctl->num_used;
-  const uint32_t* sorted = bufs.sorted();
-  int64_t lo = 0, hi = u;  // first position in [lo, hi] whose mesh id is >= b
+  const int64_t start = vtx_off[b];
+  int64_t lo = 0, hi = u;  // first packed position whose name is >= start
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (int64_t(sorted[mid * stride]) < int64_t(b)) lo = mid + 1; else hi = mid;
+    if (int64_t(dense[mid * stride + stride - 1]) < start) lo = mid + 1; else hi = mid;
   }
   out_off[b] = lo;
+}
+
+// Hash buckets of a batch's meshes (mesh_bucket): mesh b gets the smallest
+// power-of-two count of buckets that brings its vertices per bucket down to
+// `target`, and the meshes' ranges follow each other in mesh order. One
+// workgroup.
+constexpr int kMeshBucketBlock = 1024;
+__global__ __launch_bounds__(kMeshBucketBlock) void k_mesh_buckets(const int64_t* __restrict__ off, int32_t nmesh,
+                                                                   int32_t target, uint2* __restrict__ mb) {
+  __shared__ uint32_t s_wave[kMeshBucketBlock / kWave];
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nmesh; b0 += kMeshBucketBlock) {
+    const int64_t b = b0 + threadIdx.x;
+    uint32_t cnt = 0;
+    if (b < nmesh) {
+      const int64_t nb = off[b + 1] - off[b];
+      int k = 0;
+      while (k < 30 && (nb >> k) > target) ++k;
+      cnt = 1u << k;
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<kMeshBucketBlock>(cnt, s_wave, &total);
+    if (b < nmesh) mb[b] = make_uint2(carry + ex, cnt - 1u);
+    carry += total;
+  }
 }
 
 __global__ void k_localize_new2old(int32_t* __restrict__ new2old, const int64_t* __restrict__ total_used,
@@ -200,11 +228,10 @@ bool use_hash_groups(int64_t n, int32_t nmesh, const mrx_tuning* t) {
   return n >= kHashMinDefault;
 }
 
-// Hash grouping for a batch (key = (mesh id, record))? The used values are
-// then sorted by K + 1 key words, so records of 16 words have no such path.
-// Not the default: chosen by the caller or the autotuner.
-bool use_batched_hash(int64_t n, int K, int32_t nmesh, const mrx_tuning* t) {
-  if (nmesh < 2 || K >= 16 || n <= 0 || n >= kCompactLookbackLimit) return false;
+// Hash grouping for a batch (key = (mesh id, record))? Not the default:
+// chosen by the caller or the autotuner.
+bool use_batched_hash(int64_t n, int32_t nmesh, const mrx_tuning* t) {
+  if (nmesh < 2 || n <= 0 || n >= kCompactLookbackLimit) return false;
   return t && (t->flags & MRX_TUNING_HASH_GROUPS);
 }
 
@@ -263,14 +290,7 @@ struct Layout {
   int K = 0, S = 0, P_key = 0, P_mesh = 0, P_hash = 0;  // P_hash > 0: hash grouping
   BandPlan band;                                         // hash grouping only
   int64_t tiles_sort = 0, tiles_scan = 0, tiles_group = 0;
-  // hash grouping of a batch: the (mesh id, record) sort of the used values
-  // runs in the K + 1 build (P_key2 passes over tiles_sort2 tiles, its own
-  // histograms hist2 and plan plan2); the 32-bit look-back buffers are
-  // lb_half words apart
-  bool mesh_hash = false;
-  int P_key2 = 0;
-  int64_t tiles_sort2 = 0, lb_half = 0;
-  size_t hist2 = 0, plan2 = 0;
+  bool mesh_hash = false;  // hash grouping of a batch (key = (mesh id, record))
   // zeroed region
   size_t ctl = 0, counters = 0, hist = 0, plan = 0, lookback = 0, scan_lookback = 0, elem_lookback = 0,
          used_v = 0, used_g = 0, hist_hash = 0, plan_hash = 0, dead_hash = 0, group_chunks = 0, group_ranges = 0,
@@ -278,7 +298,7 @@ struct Layout {
   int64_t tiles_elem = 0;
   // scratch
   size_t buf_a = 0, buf_b = 0, buf_c = 0, uniq = 0, rep = 0, cmap = 0, vtx_tab = 0, elem_tab = 0, band_tab = 0,
-         total = 0;
+         mesh_bk = 0, total = 0;
   int64_t vtx_tab_n = 0, elem_tab_n = 0;
 };
 
@@ -295,36 +315,31 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   L.S = K + 1;
   L.P_key = (32 * K + v.D - 1) / v.D;
   L.P_mesh = nmesh > 1 ? (bits_for(int64_t(nmesh) - 1) + v.D - 1) / v.D : 0;
-  const SortVariant* w = use_batched_hash(n, K, nmesh, tuning) && v.group_mesh ? &variants_for(K + 1)[0] : nullptr;
-  L.mesh_hash = w != nullptr;
+  int ph_mesh = 0;
+  if (use_batched_hash(n, nmesh, tuning)) {
+    // every mesh's bucket count is at most 1 + 2 n_b / target (k_mesh_buckets)
+    const int64_t buckets = int64_t(nmesh) + 2 * n / v.group_mesh_target_bucket + 1;
+    ph_mesh = (bits_for(buckets) + v.D - 1) / v.D;
+    L.mesh_hash = ph_mesh <= 3;  // more than 2^24 buckets: sort all
+  }
   if (L.mesh_hash)
-    L.P_hash = hash_passes(n, v.D, v.group_mesh_target_bucket);
+    L.P_hash = ph_mesh;
   else
     L.P_hash = use_hash_groups(n, nmesh, tuning) ? hash_passes(n, v.D, v.group_target_bucket) : 0;
   L.tiles_sort = (n + v.tile() - 1) / v.tile();
   L.tiles_scan = (n + kScanTile - 1) / kScanTile;
   const int group_chunk = L.mesh_hash ? v.group_mesh_chunk : v.group_chunk;
   L.tiles_group = L.P_hash ? (n + group_chunk - 1) / group_chunk : 0;
-  if (L.mesh_hash) {
-    L.P_key2 = (32 * (K + 1) + w->D - 1) / w->D;
-    L.tiles_sort2 = (n + w->tile() - 1) / w->tile();
-  }
   const int P = L.P_key + L.P_mesh;
   size_t off = 0;
   L.ctl = off;      off = align_up(off + sizeof(Control));
   // tile counters of every look-back launch of a call (claimed tiles)
-  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + L.P_hash + L.P_key2 + 8));
+  L.counters = off; off = align_up(off + sizeof(uint32_t) * size_t(P + L.P_hash + 8));
   L.hist = off;     off = align_up(off + sizeof(uint32_t) * size_t(P) * size_t(v.radix()));
   L.plan = off;     off = align_up(off + sizeof(uint32_t) * size_t(2 * P + 1));  // SortBuffers::plan
-  if (L.mesh_hash) {
-    L.hist2 = off;  off = align_up(off + sizeof(uint32_t) * size_t(L.P_key2) * size_t(w->radix()));
-    L.plan2 = off;  off = align_up(off + sizeof(uint32_t) * size_t(2 * L.P_key2 + 1));
-  }
   // sort look-back: tiles x radix 64-bit words, or two alternating buffers of
   // 32-bit words in the same bytes; flag scan and compaction have their own
-  const int64_t lb_words = std::max<int64_t>({L.tiles_sort * v.radix(), L.mesh_hash ? L.tiles_sort2 * w->radix() : 0,
-                                              int64_t(1)});
-  L.lb_half = lb_words;
+  const int64_t lb_words = std::max<int64_t>(L.tiles_sort * v.radix(), 1);
   L.lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(lb_words));
   L.scan_lookback = off; off = align_up(off + sizeof(uint64_t) * size_t(L.tiles_scan + 1));
   L.tiles_elem = (num_idx + kSelectTile - 1) / kSelectTile;
@@ -341,13 +356,10 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   // it out of the clearing
   L.used_v = off;   off = align_up(off + size_t(n));
   L.zero_end = off;
-  // elements of K + 1 words; a batch's hash grouping also keeps (mesh id,
-  // record, group) elements of K + 2 words in them
-  const size_t ew = size_t(L.mesh_hash ? L.S + 1 : L.S);
-  L.buf_a = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * ew);
-  L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * ew);
+  L.buf_a = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
+  L.buf_b = off;    off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   if (L.P_hash) {
-    L.buf_c = off;  off = align_up(off + sizeof(uint32_t) * size_t(n) * ew);
+    L.buf_c = off;  off = align_up(off + sizeof(uint32_t) * size_t(n) * L.S);
   }
   if (nmesh == 1) {
     // by default only with hash grouping, the strategy for meshes whose
@@ -367,6 +379,9 @@ Layout make_layout(int64_t n, int64_t num_idx, int K, int32_t nmesh, const SortV
   if (nmesh > 1) {
     L.vtx_tab_n = (std::max<int64_t>(n, 1) - 1) / (int64_t(1) << kMeshTabShift) + 2;
     L.vtx_tab = off;  off = align_up(off + sizeof(int32_t) * size_t(L.vtx_tab_n));
+  }
+  if (L.mesh_hash) {
+    L.mesh_bk = off;  off = align_up(off + sizeof(uint2) * size_t(nmesh));
   }
   L.total = off;
   return L;
@@ -905,24 +920,24 @@ mrx_status launch_single(const SortVariant& v, const Layout& L, const void* vtx,
   return check_launch();
 }
 
-// The hash-grouping launch sequence of a batch. It is launch_hash's with
-// vertices told apart by (mesh id, record) instead of the record: the hash
-// digits, the grouping in LDS and the key sort of the used values all take
-// the mesh id (the mesh whose vertex range holds the id) as the most
-// significant key word, so that vertices of different meshes never group and
-// the used values come out ordered by mesh, then record. The used values'
-// elements are (mesh id, record, group) and are sorted by the K + 1 build
-// (`w`); the output offsets of the meshes are found in that sorted order.
-// New ids are numbered over the whole batch first and made mesh-local by
-// the old2new scatter and the new2old pass. A bucket that does not fit makes
-// the device take the batched sort-all path over the hash-ordered elements
-// (key and mesh-id passes, flags, scans, compaction) instead.
-mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const Layout& L, const void* vtx,
-                               const int64_t* vtx_offsets, int64_t n, int32_t vtx_bytes, const int32_t* idx,
-                               const int64_t* elem_offsets, int64_t total_elems, int32_t arity,
-                               int32_t num_meshes, void* out_vtx, int64_t* out_vtx_offsets, int32_t* out_idx,
-                               int32_t* old2new, int32_t* new2old, int32_t* dev_status, void* workspace,
-                               const mrx_tuning* tuning, void* stream_) {
+// The hash-grouping launch sequence of a batch: launch_hash's, with
+// vertices told apart by (mesh id, record). The hash digits are those of a
+// bucket of the vertex's mesh (each mesh owns a range of buckets, in mesh
+// order), so the hash-ordered elements are grouped by mesh; the grouping
+// compares (mesh id, record) in LDS and names each group by the sorted
+// position of its first copy, which lies in its mesh's vertex range. The
+// packed used elements are thus in mesh order, which gives the output
+// offsets, and the key sort of the used values adds the mesh-id passes of
+// the batched sort-all path (the mesh of an element is that of its name).
+// New ids are numbered over the whole batch and made mesh-local by the
+// old2new scatter and the new2old pass. A bucket that does not fit makes the
+// device sort all N hash-ordered elements by (mesh id, record) instead and
+// finish with the batched flags, scans and compaction.
+mrx_status launch_batched_hash(const SortVariant& v, const Layout& L, const void* vtx, const int64_t* vtx_offsets,
+                               int64_t n, int32_t vtx_bytes, const int32_t* idx, const int64_t* elem_offsets,
+                               int64_t total_elems, int32_t arity, int32_t num_meshes, void* out_vtx,
+                               int64_t* out_vtx_offsets, int32_t* out_idx, int32_t* old2new, int32_t* new2old,
+                               int32_t* dev_status, void* workspace, const mrx_tuning* tuning, void* stream_) {
   const int K = vtx_bytes / 4;
   const int64_t m = total_elems * arity;
   const int ph = L.P_hash;
@@ -933,8 +948,6 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
   uint32_t* plan = reinterpret_cast<uint32_t*>(ws + L.plan);
-  uint32_t* hist2 = reinterpret_cast<uint32_t*>(ws + L.hist2);
-  uint32_t* plan2 = reinterpret_cast<uint32_t*>(ws + L.plan2);
   uint32_t* hist_hash = reinterpret_cast<uint32_t*>(ws + L.hist_hash);
   uint32_t* plan_hash = reinterpret_cast<uint32_t*>(ws + L.plan_hash);
   uint32_t* dead_hash = reinterpret_cast<uint32_t*>(ws + L.dead_hash);
@@ -946,7 +959,7 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   const bool wide = wide_lookback(n, tuning);
   const bool claimed = tuning && (tuning->flags & MRX_TUNING_CLAIMED_TILES);
   uint32_t* const lb32[2] = {reinterpret_cast<uint32_t*>(lookback),
-                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.lb_half)};
+                             reinterpret_cast<uint32_t*>(lookback) + size_t(L.tiles_sort) * v.radix()};
   uint8_t* used_v = reinterpret_cast<uint8_t*>(ws + L.used_v);
   uint8_t* used_g = reinterpret_cast<uint8_t*>(ws + L.used_g);
   uint32_t* buf[3] = {reinterpret_cast<uint32_t*>(ws + L.buf_a), reinterpret_cast<uint32_t*>(ws + L.buf_b),
@@ -954,8 +967,9 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   uint32_t* uniq = reinterpret_cast<uint32_t*>(ws + L.uniq);
   int32_t* rep = reinterpret_cast<int32_t*>(ws + L.rep);
   int32_t* cmap = reinterpret_cast<int32_t*>(ws + L.cmap);
-  int32_t* vtab = L.vtx_tab_n ? reinterpret_cast<int32_t*>(ws + L.vtx_tab) : nullptr;
+  int32_t* vtab = reinterpret_cast<int32_t*>(ws + L.vtx_tab);
   int32_t* etab = L.elem_tab_n ? reinterpret_cast<int32_t*>(ws + L.elem_tab) : nullptr;
+  uint2* mbk = reinterpret_cast<uint2*>(ws + L.mesh_bk);
   int32_t* status = dev_status;
   int counter = 0;  // next tile counter (claimed tiles)
   auto next_counter = [&]() { return claimed ? counters + counter++ : nullptr; };
@@ -964,7 +978,7 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(int64_t(L.zero_end / 16), 256, 4096)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(ws), int64_t(L.zero_end / 16), dev_status,
                      static_cast<int64_t*>(nullptr), static_cast<int64_t*>(nullptr));
-  // n > 0 here (use_batched_hash)
+  // n > 0 and num_meshes > 1 here (use_batched_hash)
   prof_mark("mesh_tables", s);
   hipLaunchKernelGGL(k_mesh_table, dim3((L.vtx_tab_n + 255) / 256), dim3(256), 0, s, vtx_offsets, num_meshes, n,
                      vtab, L.vtx_tab_n);
@@ -976,16 +990,16 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   } else {
     etab = nullptr;
   }
-  // Step 1 (scattered byte stores; reports out-of-range entries)
-  if (m > 0) {
-    const MarkArgs mark{idx, m, arity, n, vtx_offsets, elem_offsets, num_meshes, etab, nullptr, used_v, status};
-    prof_mark("mark_used", s);
-    hipLaunchKernelGGL((k_mark_used<true>), dim3(rand_grid(m)), dim3(kRandBlock), 0, s, mark);
-  }
-  // stable sort of (record, id | used << 31) by the hash digits of
-  // (mesh id, record)
-  prof_mark("hash_histogram", s);
-  v.hash_mesh_hist(static_cast<const uint32_t*>(vtx), n, vtx_offsets, num_meshes, vtab, ph, hist_hash, s);
+  prof_mark("mesh_buckets", s);
+  hipLaunchKernelGGL(k_mesh_buckets, dim3(1), dim3(kMeshBucketBlock), 0, s, vtx_offsets, num_meshes,
+                     int32_t(v.group_mesh_target_bucket), mbk);
+  // Step 1 (scattered byte stores; reports out-of-range entries) beside the
+  // bucket-digit histograms of the stable sort of (record, id | used << 31)
+  // by the buckets of (mesh id, record)
+  const MarkArgs mark{idx, m, arity, n, vtx_offsets, elem_offsets, num_meshes, etab, nullptr, used_v, status};
+  prof_mark(m > 0 ? "mark_histogram" : "hash_histogram", s);
+  v.hash_mesh_hist(m > 0 ? &mark : nullptr, static_cast<const uint32_t*>(vtx), n, vtx_offsets, num_meshes, vtab, mbk,
+                   ph, hist_hash, s);
   prof_mark("scan_buckets", s);
   v.scan(hist_hash, ph, n, nullptr, dead_hash, s);
   const SortBuffers sbh{{buf[0], buf[1]}, plan_hash, ph};
@@ -1005,6 +1019,7 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
     a.n = n;
     a.mesh_off = vtx_offsets;
     a.mesh_tab = vtab;
+    a.mesh_buckets = mbk;
     a.nmesh = num_meshes;
     a.lo_word = a.hi_word = -1;
     a.shift = p * v.D;
@@ -1016,11 +1031,10 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   uint32_t* Y = buf[((ph - 1) & 1) ^ 1];
   uint2* pairs = reinterpret_cast<uint2*>(Y);
 
-  // group each hash bucket by (mesh id, record)
+  // group each bucket by (mesh id, record)
   GroupArgs g{};
   g.elems = X;
   g.n = n;
-  g.bucket_mask = ph * v.D >= 32 ? 0xFFFFFFFFu : (1u << (ph * v.D)) - 1u;
   g.pairs = pairs;
   g.rep = rep;
   g.cmap = cmap;
@@ -1031,73 +1045,34 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   g.status = status;
   g.mesh_off = vtx_offsets;
   g.mesh_tab = vtab;
+  g.mesh_buckets = mbk;
   g.nmesh = num_meshes;
   prof_mark("group", s);
   v.group_mesh(g, L.tiles_group, s);
-  // totals; on the grouping path the used groups' (mesh id, record, group)
-  // elements packed into X with their key-digit histograms
-  const GroupCompactArgs gc{buf[2], group_chunks, group_range_sums, L.tiles_group, group_ranges, n, X, hist2, ctl};
+
+  // key sort of X by (mesh id, record): the used groups' (record, name)
+  // elements packed from C in name order (or, on the fallback path, all N
+  // hash-ordered (record, id) elements)
+  const SortBuffers sbk{{X, buf[2]}, plan, P};
+  const GroupCompactArgs gc{buf[2], group_chunks, group_range_sums, L.tiles_group, group_ranges, n, X, hist, ctl};
   prof_mark("compact_histogram", s);
-  w.group_compact_hist(gc, s);
-  const int gp0 = gp;  // both key sorts start here; only one of them runs
-
-  // grouping path: sort the used groups by (mesh id, record) (K + 1 build)
-  const SortBuffers sba{{X, buf[2]}, plan2, L.P_key2};
-  prof_mark("scan_buckets", s);
-  w.scan(hist2, L.P_key2, n, &ctl->group_count, plan2 + L.P_key2 + 1, s);
-  prof_mark("sort_plan", s);
-  hipLaunchKernelGGL(k_group_sort_plan, dim3(1), dim3(64), 0, s, sba, static_cast<const Control*>(ctl));
-  for (int p = 0; p < L.P_key2; ++p, ++gp) {
-    SortPassArgs a{};
-    a.bufs = sba;
-    a.pass = p;
-    a.bucket_base = hist2 + size_t(p) * w.radix();
-    a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[gp & 1]);
-    a.lookback_next = lb32[(gp + 1) & 1];
-    a.tile_counter = next_counter();
-    a.ctl = ctl;
-    a.status = status;
-    a.n = n;
-    a.n_dev = &ctl->group_count;
-    set_digit(a, K + 1, p * w.D);
-    a.tag = uint32_t(gp + 1);
-    prof_mark("onesweep", s);
-    w.pass(a, kPassKey, wide, L.tiles_sort2, s);
-  }
-  const int gp_a = gp;
-  FinalizeArgs fa{};
-  fa.bufs = sba;
-  fa.rep = rep;
-  fa.cmap = cmap;
-  fa.out_vtx = static_cast<uint32_t*>(out_vtx);
-  fa.new2old = new2old;
-  fa.out_num = nullptr;
-  fa.cap = n;
-  fa.ctl = ctl;
-  fa.status = status;
-  fa.drop_first = 1;
-  prof_mark("finalize", s);
-  w.finalize(fa, grid_for(n, 256, 4096), s);
-  prof_mark("batch_offsets", s);
-  hipLaunchKernelGGL(k_batch_offsets_sorted, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, sba,
-                     int32_t(K + 2), static_cast<const Control*>(ctl), num_meshes, out_vtx_offsets);
-
-  // fallback path: key and mesh-id passes over all N hash-ordered elements,
-  // then the batched flags, scans and compaction
-  gp = gp0;
-  const SortBuffers sbb{{X, buf[2]}, plan, P};
+  v.group_compact_hist(gc, s);
   const HistArgs ha{{X, X}, nullptr, n, &ctl->all_count, hist};
   prof_mark("histogram", s);
   v.elem_hist(ha, s);
+  prof_mark("batch_offsets", s);
+  hipLaunchKernelGGL(k_batch_offsets_dense, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s,
+                     static_cast<const uint32_t*>(X), int32_t(K + 1), static_cast<const Control*>(ctl), vtx_offsets,
+                     num_meshes, out_vtx_offsets);
   prof_mark("mesh_histogram", s);
-  v.mesh_hist(vtx_offsets, num_meshes, L.P_mesh, hist + size_t(L.P_key) * v.radix(), s);
+  v.mesh_hist_path(out_vtx_offsets, vtx_offsets, ctl, num_meshes, L.P_mesh, hist + size_t(L.P_key) * v.radix(), s);
   prof_mark("scan_buckets", s);
-  v.scan(hist, P, n, &ctl->all_count, plan + P + 1, s);
+  v.scan(hist, P, n, &ctl->sort_count, plan + P + 1, s);
   prof_mark("sort_plan", s);
-  hipLaunchKernelGGL(k_group_sort_plan, dim3(1), dim3(64), 0, s, sbb, static_cast<const Control*>(ctl));
+  hipLaunchKernelGGL(k_group_sort_plan, dim3(1), dim3(64), 0, s, sbk, static_cast<const Control*>(ctl));
   for (int p = 0; p < P; ++p, ++gp) {
     SortPassArgs a{};
-    a.bufs = sbb;
+    a.bufs = sbk;
     a.pass = p;
     a.bucket_base = hist + size_t(p) * v.radix();
     a.lookback = wide ? static_cast<void*>(lookback) : static_cast<void*>(lb32[gp & 1]);
@@ -1106,7 +1081,7 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
     a.ctl = ctl;
     a.status = status;
     a.n = n;
-    a.n_dev = &ctl->all_count;
+    a.n_dev = &ctl->sort_count;
     a.mesh_off = vtx_offsets;
     a.mesh_tab = vtab;
     a.nmesh = num_meshes;
@@ -1121,9 +1096,22 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
     prof_mark(mode == kPassMesh ? "onesweep_mesh" : "onesweep", s);
     v.pass(a, mode, wide, L.tiles_sort, s);
   }
-  const int gp_end = std::max(gp, gp_a);
+  // grouping path: sorted position = new id over the whole batch
+  FinalizeArgs fa{};
+  fa.bufs = sbk;
+  fa.rep = rep;
+  fa.cmap = cmap;
+  fa.out_vtx = static_cast<uint32_t*>(out_vtx);
+  fa.new2old = new2old;
+  fa.out_num = nullptr;
+  fa.cap = n;
+  fa.ctl = ctl;
+  fa.status = status;
+  prof_mark("finalize", s);
+  v.finalize(fa, grid_for(n, 256, 4096), s);
+  // fallback path: the batched flags, scans and compaction over all of X
   FlagScanArgs f{};
-  f.bufs = sbb;
+  f.bufs = sbk;
   f.n = n;
   f.uniq = uniq;
   f.rep = rep;
@@ -1135,7 +1123,7 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   f.mesh_off = vtx_offsets;
   f.mesh_tab = vtab;
   f.nmesh = num_meshes;
-  f.tag = uint32_t(gp_end + 1);
+  f.tag = uint32_t(gp + 1);
   f.pairs = pairs;
   f.gate = kGateSortAll;
   prof_mark("flag_scan", s);
@@ -1154,13 +1142,13 @@ mrx_status launch_batched_hash(const SortVariant& v, const SortVariant& w, const
   c.tile_counter = next_counter();
   c.ctl = ctl;
   c.status = status;
-  c.tag = uint32_t(gp_end + 2);
+  c.tag = uint32_t(gp + 2);
   c.gate = kGateSortAll;
   prof_mark("compact", s);
   hipLaunchKernelGGL((k_compact<kScanBlock, kScanIpt>), dim3(L.tiles_scan), dim3(kScanBlock), 0, s, c);
   prof_mark("batch_offsets", s);
   hipLaunchKernelGGL(k_batch_offsets, dim3((num_meshes + 1 + 255) / 256), dim3(256), 0, s, vtx_offsets, num_meshes,
-                     sbb, static_cast<const uint2*>(pairs), static_cast<const int32_t*>(cmap),
+                     sbk, static_cast<const uint2*>(pairs), static_cast<const int32_t*>(cmap),
                      static_cast<const Control*>(ctl), static_cast<const int64_t*>(&ctl->num_used), n,
                      int32_t(kGateSortAll), out_vtx_offsets);
 
@@ -1370,9 +1358,9 @@ mrx_status mrx_reindex_mesh_batched(const void* vtx, const int64_t* vtx_offsets,
     return MRX_ERR_INVALID_ARGUMENT;
 
   if (L.mesh_hash)
-    return launch_batched_hash(v, variants_for(K + 1)[0], L, vtx, vtx_offsets, n, vtx_bytes, idx, elem_offsets,
-                               total_elems, arity, num_meshes, out_vtx, out_vtx_offsets, out_idx, old2new, new2old,
-                               dev_status, workspace, tuning, stream_);
+    return launch_batched_hash(v, L, vtx, vtx_offsets, n, vtx_bytes, idx, elem_offsets, total_elems, arity,
+                               num_meshes, out_vtx, out_vtx_offsets, out_idx, old2new, new2old, dev_status,
+                               workspace, tuning, stream_);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
   char* ws = static_cast<char*>(workspace);
   Control* ctl = reinterpret_cast<Control*>(ws + L.ctl);

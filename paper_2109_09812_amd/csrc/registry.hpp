@@ -86,12 +86,16 @@ struct SortVariant {
   void (*finalize)(const FinalizeArgs&, int64_t grid, hipStream_t) = nullptr;
   int group_chunk = 0;           // sorted positions per grouping workgroup
   int group_target_bucket = 0;   // average bucket size the hash passes aim for
-  // hash grouping of a batch: hash-digit histograms of (mesh id, record),
-  // and the grouping by (mesh id, record) whose used elements (K + 2 words)
-  // the K + 1 build sorts (null for K = 16)
-  void (*hash_mesh_hist)(const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh, const int32_t* tab,
-                         int ph, uint32_t* hist, hipStream_t) = nullptr;
+  // hash grouping of a batch: bucket-digit histograms of (mesh id,
+  // record), the grouping by (mesh id, record), and the mesh-id digit
+  // histograms of the key sort that follows (k_mesh_histogram_path)
+  // (with Step 1's marking of the batch in the same launch when `mark` is given)
+  void (*hash_mesh_hist)(const MarkArgs* mark, const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh,
+                         const int32_t* tab, const uint2* mesh_buckets, int ph, uint32_t* hist,
+                         hipStream_t) = nullptr;
   void (*group_mesh)(const GroupArgs&, int64_t grid, hipStream_t) = nullptr;
+  void (*mesh_hist_path)(const int64_t* off_grouped, const int64_t* off_all, const Control* ctl, int32_t nmesh,
+                         int32_t passes, uint32_t* hist, hipStream_t) = nullptr;
   int group_mesh_chunk = 0;
   int group_mesh_target_bucket = 0;
 

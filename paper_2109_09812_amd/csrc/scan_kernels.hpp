@@ -304,7 +304,10 @@ __global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
 // pairs that the flag scan left in the spare sort buffer (or that the hash
 // grouping left in `pairs_in`); the cmap reads follow the non-decreasing
 // group ids. For a batch the new id is made mesh-local with the mesh's
-// output offset.
+// output offset. A batch's pairs are in mesh order, mesh b's at positions
+// [vtx_off[b], vtx_off[b+1]) (sorted by (mesh id, record), or hash-ordered
+// with per-mesh bucket ranges), so the mesh of an element is that of its
+// position: one lookup for a tile inside one mesh.
 template <bool BATCHED>
 __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(SortBuffers bufs, const uint2* pairs_in,
                                                                 const int32_t* __restrict__ cmap, int64_t n,
@@ -316,14 +319,20 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(SortBuffers bufs
   const uint2* __restrict__ pairs = pairs_in ? pairs_in : reinterpret_cast<const uint2*>(bufs.spare());
   __shared__ int32_t s_cmap[TILE];
   __shared__ uint32_t s_g[2];
+  __shared__ uint32_t s_mesh[2];
   const int64_t t0 = int64_t(blockIdx.x) * TILE;
   const int64_t base = t0 + threadIdx.x;
+  const int64_t t1 = min(t0 + TILE, n) - 1;  // last position of the tile
   // A tile's group ids are non-decreasing and grow by at most one per
   // position, so cmap[g_first .. g_last] (at most TILE entries) is staged in
   // LDS with coalesced loads instead of one gather per element.
   if (threadIdx.x == 0) {
     s_g[0] = pairs[t0].x;
-    s_g[1] = pairs[min(t0 + TILE, n) - 1].x;
+    s_g[1] = pairs[t1].x;
+    if constexpr (BATCHED) {
+      s_mesh[0] = mesh_of(vtx_off, nmesh, t0, vtx_tab);
+      s_mesh[1] = mesh_of(vtx_off, nmesh, t1, vtx_tab);
+    }
   }
   uint2 p[kScatterItems];
   int32_t c[kScatterItems];
@@ -348,12 +357,18 @@ __global__ __launch_bounds__(kRandBlock) void k_scatter_old2new(SortBuffers bufs
     if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) c[it] = -1;
     else c[it] = (off >= 0 && off < span) ? s_cmap[off] : cmap[p[it].x];  // outside: only after a failed wait
   }
+  int64_t tile_off = 0;  // output offset of the tile's mesh, if it has one
+  const bool one_mesh = BATCHED && s_mesh[0] == s_mesh[1];
+  if constexpr (BATCHED) {
+    if (one_mesh) tile_off = out_off[s_mesh[0]];
+  }
 #pragma unroll
   for (int it = 0; it < kScatterItems; ++it) {
     if (int64_t(p[it].x) >= n || int64_t(p[it].y) >= n) continue;  // past the end (or a failed wait)
     int32_t cc = c[it] < 0 ? -1 : c[it];
     if constexpr (BATCHED) {
-      if (cc >= 0) cc -= int32_t(out_off[mesh_of(vtx_off, nmesh, int64_t(p[it].y), vtx_tab)]);
+      if (cc >= 0)
+        cc -= int32_t(one_mesh ? tile_off : out_off[mesh_of(vtx_off, nmesh, base + it * kRandBlock, vtx_tab)]);
     }
     old2new[p[it].y] = cc;
   }

@@ -170,24 +170,48 @@ void launch_hash_hist(const MarkArgs* ma, const uint32_t* vtx, int64_t n, int ph
 
 // Hash-digit histograms of a batch's records (hash of (mesh id, record)),
 // on a capped grid of workgroups that each walk several chunks.
+// Step 1's marking of a batch (mark_used_tile) and the bucket-digit
+// histograms in one launch: the histogram workgroups (few, long, bound by
+// the hash and LDS atomics) come first in the grid and the marking tiles
+// (many, short, bound by scattered byte stores) fill the rest of the GPU
+// beside them.
 template <int D, int PH>
-void launch_hash_mesh_hist_ph(const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh, const int32_t* tab,
-                              uint32_t* hist, hipStream_t s) {
-  constexpr int B = 256, GROUPS = kHistGroups;
+__global__ __launch_bounds__(kRandBlock) void k_mark_hash_mesh_hist(MarkArgs ma, const uint32_t* __restrict__ vtx,
+                                                                    int64_t n, const int64_t* __restrict__ off,
+                                                                    int32_t nmesh, const int32_t* __restrict__ tab,
+                                                                    const uint2* __restrict__ mb,
+                                                                    uint32_t* __restrict__ hist, int64_t hist_blocks) {
+  __shared__ uint32_t s_h[PH << D];
+  const int64_t b = blockIdx.x;
+  if (b < hist_blocks)
+    hash_mesh_hist_block<K, D, PH, kRandBlock, kHistGroups>(vtx, n, off, nmesh, tab, mb, hist, b, hist_blocks, s_h);
+  else
+    mark_used_tile<true>(ma, b - hist_blocks);
+}
+
+template <int D, int PH>
+void launch_hash_mesh_hist_ph(const MarkArgs* ma, const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh,
+                              const int32_t* tab, const uint2* mb, uint32_t* hist, hipStream_t s) {
+  constexpr int B = kRandBlock, GROUPS = kHistGroups;
   const int64_t per_block = int64_t(B) * GROUPS;
   const int64_t grid = std::min((n + per_block - 1) / per_block, kElemHistGrid);
-  if (grid > 0)
+  if (ma && ma->m > 0) {
+    const int64_t mt = (ma->m + kRandBlock * kRandItems - 1) / (kRandBlock * kRandItems);
+    hipLaunchKernelGGL((k_mark_hash_mesh_hist<D, PH>), dim3(grid + mt), dim3(B), 0, s, *ma, vtx, n, off, nmesh, tab,
+                       mb, hist, grid);
+  } else if (grid > 0) {
     hipLaunchKernelGGL((k_hash_mesh_histogram<K, D, PH, B, GROUPS>), dim3(grid), dim3(B), 0, s, vtx, n, off, nmesh,
-                       tab, hist);
+                       tab, mb, hist);
+  }
 }
 
 template <int D>
-void launch_hash_mesh_hist(const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh, const int32_t* tab,
-                           int ph, uint32_t* hist, hipStream_t s) {
+void launch_hash_mesh_hist(const MarkArgs* ma, const uint32_t* vtx, int64_t n, const int64_t* off, int32_t nmesh,
+                           const int32_t* tab, const uint2* mb, int ph, uint32_t* hist, hipStream_t s) {
   switch (ph) {
-    case 1: launch_hash_mesh_hist_ph<D, 1>(vtx, n, off, nmesh, tab, hist, s); break;
-    case 2: launch_hash_mesh_hist_ph<D, 2>(vtx, n, off, nmesh, tab, hist, s); break;
-    default: launch_hash_mesh_hist_ph<D, 3>(vtx, n, off, nmesh, tab, hist, s); break;
+    case 1: launch_hash_mesh_hist_ph<D, 1>(ma, vtx, n, off, nmesh, tab, mb, hist, s); break;
+    case 2: launch_hash_mesh_hist_ph<D, 2>(ma, vtx, n, off, nmesh, tab, mb, hist, s); break;
+    default: launch_hash_mesh_hist_ph<D, 3>(ma, vtx, n, off, nmesh, tab, mb, hist, s); break;
   }
 }
 
@@ -201,13 +225,21 @@ void launch_group(const GroupArgs& a, int64_t grid, hipStream_t s) {
   if (grid > 0) hipLaunchKernelGGL((k_group<K, false>), dim3(grid), dim3(GroupShape<K>::BLOCK), 0, s, a);
 }
 
-// Grouping by (mesh id, record) for a batch; its elements go on to the sort
-// of K + 1 key words (the K + 1 build), so the widest records have none.
-#if MRX_INST_K < 16
+// Grouping by (mesh id, record) for a batch (the shape of K + 1-word keys).
 void launch_group_mesh(const GroupArgs& a, int64_t grid, hipStream_t s) {
   if (grid > 0) hipLaunchKernelGGL((k_group<K, true>), dim3(grid), dim3(GroupShape<K + 1>::BLOCK), 0, s, a);
 }
-#endif
+
+// Mesh-id digit histograms of a batch's key sort after its hash grouping:
+// per-mesh counts from the used values' offsets (grouping path) or the
+// vertex offsets (everything sorted).
+template <int D>
+void launch_mesh_hist_path(const int64_t* off_grouped, const int64_t* off_all, const Control* ctl, int32_t nmesh,
+                           int32_t passes, uint32_t* hist, hipStream_t s) {
+  if (nmesh <= 0 || passes <= 0) return;
+  hipLaunchKernelGGL((k_mesh_histogram_path<D>), dim3((nmesh + 255) / 256), dim3(256), 0, s, off_grouped, off_all,
+                     ctl, nmesh, passes, hist);
+}
 
 void launch_finalize(const FinalizeArgs& a, int64_t grid, hipStream_t s) {
   if (grid > 0) hipLaunchKernelGGL((k_group_finalize<K>), dim3(grid), dim3(256), 0, s, a);
@@ -292,11 +324,10 @@ SortVariant make() {
   v.group_chunk = GroupShape<K>::CHUNK;
   v.group_target_bucket = GroupShape<K>::TARGET_BUCKET;
   v.hash_mesh_hist = &launch_hash_mesh_hist<D>;
-#if MRX_INST_K < 16
+  v.mesh_hist_path = &launch_mesh_hist_path<D>;
   v.group_mesh = &launch_group_mesh;
   v.group_mesh_chunk = GroupShape<K + 1>::CHUNK;
   v.group_mesh_target_bucket = GroupShape<K + 1>::TARGET_BUCKET;
-#endif
   return v;
 }
 

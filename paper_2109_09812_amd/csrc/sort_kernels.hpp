@@ -40,11 +40,13 @@ struct SortPassArgs {
   int32_t* status;
   const int64_t* mesh_off;      // mesh and mesh-hash passes: [nmesh+1] vertex offsets
   const int32_t* mesh_tab;      // mesh passes: bucket table of mesh_off (mesh_of)
+  const uint2* mesh_buckets;    // mesh-hash passes: each mesh's hash buckets (mesh_bucket)
   const int64_t* n_dev;         // non-null: the element count is min(n, *n_dev), read on the device
   int32_t nmesh;
   // Key passes: the digit is bits [shift, shift + D) of (w[hi_word]:w[lo_word])
-  // (hi_word < 0: none). Hash passes: bits [shift, shift + D) of the hash;
-  // mesh passes: of the mesh id.
+  // (hi_word < 0: none). Hash passes: bits [shift, shift + D) of the hash
+  // (mesh-hash passes: of the bucket of (mesh id, record)); mesh passes: of
+  // the mesh id.
   int32_t lo_word, hi_word;
   int32_t shift;
   int64_t n;
@@ -234,38 +236,62 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(HistArgs a) {
   flush_histograms<WORDS, BLOCK>(s_h, a.hist);
 }
 
-// Hash-digit histograms of a batch's records for the PH hash passes of its
+// Digits of the PH passes over one word (w[0]).
+template <int D, int PH>
+struct WordDigits {
+  static constexpr int kPasses = PH;
+  static __device__ __forceinline__ void digits(const uint32_t* w, uint32_t (&d)[kPasses]) {
+#pragma unroll
+    for (int p = 0; p < PH; ++p) d[p] = (w[0] >> (p * D)) & ((1u << D) - 1u);
+  }
+};
+
+// Bucket-digit histograms of a batch's records for the PH hash passes of its
 // hash grouping: record i is hashed together with its mesh id (the mesh
-// whose vertex range holds i), as the hash passes and the grouping do.
+// whose vertex range holds i) and falls in one of that mesh's buckets, as in
+// the hash passes and the grouping.
+// One workgroup's share (block hb of nb, walking chunks hb, hb + nb, ...);
+// s_h holds PH << D words of LDS.
 template <int K, int D, int PH, int BLOCK, int GROUPS>
-__global__ __launch_bounds__(BLOCK) void k_hash_mesh_histogram(const uint32_t* __restrict__ vtx, int64_t n,
-                                                               const int64_t* __restrict__ off, int32_t nmesh,
-                                                               const int32_t* __restrict__ tab,
-                                                               uint32_t* __restrict__ hist) {
-  using DG = HashDigits<K + 1, D, PH>;
+__device__ __forceinline__ void hash_mesh_hist_block(const uint32_t* __restrict__ vtx, int64_t n,
+                                                     const int64_t* __restrict__ off, int32_t nmesh,
+                                                     const int32_t* __restrict__ tab, const uint2* __restrict__ mb,
+                                                     uint32_t* __restrict__ hist, int64_t hb, int64_t nb,
+                                                     uint32_t* s_h) {
+  using DG = WordDigits<D, PH>;
   constexpr int WORDS = PH << D;
-  __shared__ uint32_t s_h[WORDS];
   const int64_t chunks = (n + BLOCK * GROUPS - 1) / (BLOCK * GROUPS);
-  if (int64_t(blockIdx.x) >= chunks) return;  // whole block
+  if (hb >= chunks) return;  // whole block
   zero_histograms<WORDS, BLOCK>(s_h);
   uint32_t last[PH], run[PH];
 #pragma unroll
   for (int p = 0; p < PH; ++p) { last[p] = 0; run[p] = 0; }
-  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+  for (int64_t c = hb; c < chunks; c += nb) {
     for (int it = 0; it < GROUPS; ++it) {
       const int64_t i = c * (BLOCK * GROUPS) + int64_t(it) * BLOCK + threadIdx.x;
       if (i >= n) break;
-      uint32_t x[K + 1];
-      x[0] = mesh_of(off, nmesh, i, tab);
+      uint32_t x[K];
 #pragma unroll
-      for (int w = 0; w < K; ++w) x[w + 1] = vtx[i * K + w];
-      hist_item<DG, D>(x, s_h, last, run);
+      for (int w = 0; w < K; ++w) x[w] = vtx[i * K + w];
+      const uint32_t m = mesh_of(off, nmesh, i, tab);
+      const uint32_t bucket[1] = {mesh_bucket(mb, m, hash_mesh_words<K>(m, x))};
+      hist_item<DG, D>(bucket, s_h, last, run);
     }
   }
 #pragma unroll
   for (int p = 0; p < PH; ++p)
     if (run[p]) atomicAdd(&s_h[p * (1 << D) + last[p]], run[p]);
   flush_histograms<WORDS, BLOCK>(s_h, hist);
+}
+
+template <int K, int D, int PH, int BLOCK, int GROUPS>
+__global__ __launch_bounds__(BLOCK) void k_hash_mesh_histogram(const uint32_t* __restrict__ vtx, int64_t n,
+                                                               const int64_t* __restrict__ off, int32_t nmesh,
+                                                               const int32_t* __restrict__ tab,
+                                                               const uint2* __restrict__ mb,
+                                                               uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[PH << D];
+  hash_mesh_hist_block<K, D, PH, BLOCK, GROUPS>(vtx, n, off, nmesh, tab, mb, hist, blockIdx.x, gridDim.x, s_h);
 }
 
 // Histograms of the mesh-id passes of a batch: mesh b contributes its vertex
@@ -276,6 +302,23 @@ __global__ void k_mesh_histogram(const int64_t* __restrict__ off, int32_t nmesh,
   constexpr int RADIX = 1 << D;
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nmesh) return;
+  const uint32_t cnt = uint32_t(off[b + 1] - off[b]);
+  if (cnt == 0) return;
+  for (int q = 0; q < mesh_passes; ++q)
+    atomicAdd(&hist[q * RADIX + ((uint32_t(b) >> (q * D)) & (RADIX - 1))], cnt);
+}
+
+// The same for the key sort of a batch after its hash grouping, which sorts
+// the used values (grouping path: per-mesh counts from their offsets
+// off_grouped) or every vertex (Control::path = 1: from off_all).
+template <int D>
+__global__ void k_mesh_histogram_path(const int64_t* __restrict__ off_grouped, const int64_t* __restrict__ off_all,
+                                      const Control* ctl, int32_t nmesh, int32_t mesh_passes,
+                                      uint32_t* __restrict__ hist) {
+  constexpr int RADIX = 1 << D;
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nmesh) return;
+  const int64_t* off = __builtin_amdgcn_readfirstlane(ctl->path) == 0 ? off_grouped : off_all;
   const uint32_t cnt = uint32_t(off[b + 1] - off[b]);
   if (cnt == 0) return;
   for (int q = 0; q < mesh_passes; ++q)
@@ -468,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
       if constexpr (kMeshHash) {
         const int64_t pos = wave_base + j * kWave;
         const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
-        dig[j] = (hash_mesh_words<K>(m, v[j]) >> a.shift) & MASK;
+        dig[j] = (mesh_bucket(a.mesh_buckets, m, hash_mesh_words<K>(m, v[j])) >> a.shift) & MASK;
       } else if constexpr (kHash)
         dig[j] = (hash_words<K>(v[j]) >> a.shift) & MASK;
       else

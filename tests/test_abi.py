@@ -162,14 +162,13 @@ def test_tuning_flags():
     assert _ws(2_000_000, 12, 1_500_000)[1] == _ws(2_000_000, 12, 1_500_000, tuning=(0, 0, 0, bands))[1]
     # more index entries than the element buffer holds: no bands
     assert _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed | bands))[1] == _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed))[1]
-    # batches: hash grouping by (mesh id, record) keeps three buffers of
-    # K + 2-word elements; sort-all two of K + 1 words; 16-word records have
-    # no hash grouping in a batch
+    # batches: hash grouping by (mesh id, record) needs the third buffer and
+    # the meshes' bucket table; not the default for batches
     st_b, need_b = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, hashed))
     st_bs, need_bs = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, sort_all))
-    assert st_b == st_bs == 0 and need_b >= need_bs + 100_000 * 20 and need_b > need_h
-    assert _ws(100_000, 12, 90_000, 2) == (0, need_bs)   # not the default for batches
-    assert _ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, hashed)) == _ws(100_000, 64, 90_000, 2)
+    assert st_b == st_bs == 0 and need_b >= need_bs + 100_000 * 16
+    assert _ws(100_000, 12, 90_000, 2) == (0, need_bs)
+    assert _ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, hashed))[1] > _ws(100_000, 64, 90_000, 2)[1]
 
 
 def test_workspace_one_byte_short():
@@ -280,11 +279,13 @@ def test_autotune_cache_validation(tmp_path, monkeypatch):
     assert at.cached_tuning(loaded, "c", 12) is None       # malformed
     assert at.cached_tuning(loaded, "d", 12) is None       # no strategy (older schema)
     assert at.cached_tuning(loaded, "e", 12) is None       # flags that are not a strategy choice
-    # candidates: every shape with both strategies for a single mesh, shapes only for a batch
+    # candidates: every shape with both strategies (single meshes and batches),
+    # shapes only where a call always sorts all
     single = at.candidates(12, 100_000, False)
     assert len(single) == 2 * len(_lib.tunings(12))
     assert {t.flags for t in single} == {_lib.MRX_TUNING_SORT_ALL, hashed}
-    assert {t.flags for t in at.candidates(12, 100_000, True)} == {0}
+    assert {t.flags for t in at.candidates(12, 100_000, True)} == {_lib.MRX_TUNING_SORT_ALL, hashed}
+    assert {t.flags for t in at.candidates(12, 1 << 30, True)} == {0}
     assert {t.flags for t in at.candidates(12, 1 << 30, False)} == {0}
     assert at.cached_tuning(loaded, "missing", 12) is None
     k = at.shape_key("gfx950", 12, 26_398_316, False)

@@ -75,8 +75,7 @@ def test_batched_hash_lookback_flags(fl):
 
 @pytest.mark.parametrize("words", [1, 2, 4, 5, 8, 15, 16])
 def test_batched_hash_record_widths(words):
-    """Every record width; 16-word records have no (mesh, record) sort of
-    17 words and run the sort-all path instead (same result)."""
+    """Every record width, 1 to 16 words."""
     import paper_2109_09812_amd as mrx
     sizes = [5000, 1, 0, 23_001, 777, 9000, 40_000, 2]
     b = pooled_batch(sizes, words, 70 + words)
