@@ -86,18 +86,22 @@ typedef struct {
  * assumption about dispatch order but costs a round trip per tile. */
 #define MRX_TUNING_CLAIMED_TILES 2
 
-/* Single-mesh calls find duplicates in one of two ways, with the identical
+/* Re-index calls find duplicates in one of two ways, with the identical
  * result:
  *   - sort-all: Section 2's method as printed: a stable LSD radix sort of all
- *     N (record, id) pairs by the full record, then run-head flags and scans;
+ *     N (record, id) pairs by the full record (for a batch: by (mesh id,
+ *     record)), then run-head flags and scans;
  *   - hash grouping: a stable sort of the pairs by a few hash digits of the
- *     record, grouping of equal records in on-chip memory, and the full-key
- *     sort of the U used values only (falls back to sort-all on the device
- *     when a hash bucket is too large, e.g. a value with thousands of
- *     copies).
- * Without either flag the library chooses (hash grouping for meshes of at
- * least 2^16 and fewer than 2^30 vertices); setting both is
- * MRX_ERR_UNSUPPORTED. Batched calls always sort all. */
+ *     record (for a batch: of (mesh id, record), in buckets owned by the
+ *     vertex's mesh), grouping of equal records (of one mesh) in on-chip
+ *     memory, and the full-key sort of the U used values only (falls back to
+ *     sort-all on the device when a hash bucket is too large, e.g. a value
+ *     with thousands of copies in one mesh).
+ * Without either flag the library chooses (hash grouping for meshes and
+ * batches of at least 2^16 and fewer than 2^30 vertices in all); setting
+ * both is MRX_ERR_UNSUPPORTED. A batch whose meshes would need more than
+ * 2^24 hash buckets in all (one per mesh at least, and about one per few
+ * hundred vertices) sorts all whatever the flags say. */
 #define MRX_TUNING_SORT_ALL 4
 #define MRX_TUNING_HASH_GROUPS 8
 

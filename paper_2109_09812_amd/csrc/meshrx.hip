@@ -228,11 +228,13 @@ bool use_hash_groups(int64_t n, int32_t nmesh, const mrx_tuning* t) {
   return n >= kHashMinDefault;
 }
 
-// Hash grouping for a batch (key = (mesh id, record))? Not the default:
-// chosen by the caller or the autotuner.
+// Hash grouping for a batch (key = (mesh id, record))? By default from 2^16
+// vertices in all, as for single meshes.
 bool use_batched_hash(int64_t n, int32_t nmesh, const mrx_tuning* t) {
   if (nmesh < 2 || n <= 0 || n >= kCompactLookbackLimit) return false;
-  return t && (t->flags & MRX_TUNING_HASH_GROUPS);
+  if (t && (t->flags & MRX_TUNING_SORT_ALL)) return false;
+  if (t && (t->flags & MRX_TUNING_HASH_GROUPS)) return true;
+  return n >= kHashMinDefault;
 }
 
 // Hash passes: enough D-bit hash digits that a bucket averages at most the

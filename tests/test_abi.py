@@ -163,12 +163,14 @@ def test_tuning_flags():
     # more index entries than the element buffer holds: no bands
     assert _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed | bands))[1] == _ws(1000, 4, 10_000, tuning=(0, 0, 0, hashed))[1]
     # batches: hash grouping by (mesh id, record) needs the third buffer and
-    # the meshes' bucket table; not the default for batches
+    # the meshes' bucket table; the default from 2^16 vertices in all
     st_b, need_b = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, hashed))
     st_bs, need_bs = _ws(100_000, 12, 90_000, 2, tuning=(0, 0, 0, sort_all))
     assert st_b == st_bs == 0 and need_b >= need_bs + 100_000 * 16
-    assert _ws(100_000, 12, 90_000, 2) == (0, need_bs)
-    assert _ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, hashed))[1] > _ws(100_000, 64, 90_000, 2)[1]
+    assert _ws(100_000, 12, 90_000, 2) == (0, need_b)
+    assert _ws(60_000, 12, 50_000, 2) == _ws(60_000, 12, 50_000, 2, tuning=(0, 0, 0, sort_all))
+    assert (_ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, hashed))[1] >
+            _ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, sort_all))[1])
 
 
 def test_workspace_one_byte_short():

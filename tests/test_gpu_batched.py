@@ -36,12 +36,16 @@ def check_batch(b: meshgen.Batch, res):
     assert np.array_equal(np.diff(ooff), b.expected_unique)
 
 
+SORT_ALL = 4  # MRX_TUNING_SORT_ALL; without it batches of 2^16 vertices and more use hash grouping
+
+
+@pytest.mark.parametrize("strategy", [None, (0, 0, 0, SORT_ALL)])
 @pytest.mark.parametrize("meshes,hi,seed", [(1, 3000, 1), (7, 3000, 2), (64, 20_000, 3), (300, 5_000, 4)])
-def test_batched_matches_per_mesh_oracle(meshes, hi, seed):
+def test_batched_matches_per_mesh_oracle(meshes, hi, seed, strategy):
     import paper_2109_09812_amd as mrx
     b = meshgen.batched(meshes, 100, hi, 0.05, 900 + seed)
-    _say("batch", meshes, "meshes", b.vtx.shape[0], "vertices")
-    res = mrx.reindex_mesh_batched(*to_dev(b))
+    _say("batch", meshes, "meshes", b.vtx.shape[0], "vertices", strategy)
+    res = mrx.reindex_mesh_batched(*to_dev(b), tuning=strategy)
     check_batch(b, res)
 
 
@@ -63,7 +67,8 @@ def test_batched_with_skipped_passes():
     idx = np.concatenate(idx_parts)
     eo = np.array(eo, np.int64)
     _say("batch with skipped passes", n, "vertices")
-    for t in (None, (0, 0, 0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES)):
+    for t in (None, (0, 0, 0, mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES), (0, 0, 0, SORT_ALL),
+              (0, 0, 0, SORT_ALL | mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES)):
         res = mrx.reindex_mesh_batched(torch.from_numpy(vtx.view(np.int32)).to(DEV), torch.from_numpy(vo).to(DEV),
                                        torch.from_numpy(idx).to(DEV), torch.from_numpy(eo).to(DEV), tuning=t)
         ov, ooff, oi, o2n, n2o = oracle.reindex_batched(vtx, idx, vo, eo)
@@ -121,7 +126,8 @@ def test_batched_index_out_of_range():
         mrx.reindex_mesh_batched(*to_dev(bb))
 
 
-def test_graph_replays_with_new_contents():
+@pytest.mark.parametrize("strategy", [None, (0, 0, 0, SORT_ALL)])
+def test_graph_replays_with_new_contents(strategy):
     """Capture once, refill the inputs in place, replay; every replay must be
     exact (the per-call state is cleared by a kernel inside the graph)."""
     import paper_2109_09812_amd as mrx
@@ -145,8 +151,8 @@ def test_graph_replays_with_new_contents():
         variants.append(meshgen.Batch(vtx, idx, base.vtx_offsets, base.elem_offsets,
                                       base.expected_unique, "perm"))
     tensors = to_dev(base)
-    _say("capture graph")
-    gr = mrx.GraphedBatchedReindexer(*tensors)
+    _say("capture graph", strategy)
+    gr = mrx.GraphedBatchedReindexer(*tensors, tuning=strategy)
     for rep, b in enumerate(variants + [variants[1]]):
         _say("replay", rep)
         tensors[0].copy_(torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)))
@@ -159,7 +165,8 @@ def test_graph_replays_with_new_contents():
         _ = (tensors[0].float() * 2).sum().item()
 
 
-def test_graph_replays_with_changing_skipped_passes():
+@pytest.mark.parametrize("strategy", [None, (0, 0, 0, SORT_ALL)])
+def test_graph_replays_with_changing_skipped_passes(strategy):
     """The pass plan is worked out on the device in every replay: contents
     that alternate between records with several single-digit passes and
     records with none must all come out exact."""
@@ -171,8 +178,8 @@ def test_graph_replays_with_changing_skipped_passes():
     flat[:, 1] = rng.integers(0, 5, n).astype(np.uint32) << np.uint32(8)     # one live key pass
     few = meshgen.Batch(flat.view(np.float32), base.idx, base.vtx_offsets, base.elem_offsets, None, "few")
     tensors = to_dev(base)
-    _say("capture graph (skipped passes)")
-    gr = mrx.GraphedBatchedReindexer(*tensors)
+    _say("capture graph (skipped passes)", strategy)
+    gr = mrx.GraphedBatchedReindexer(*tensors, tuning=strategy)
     for rep, b in enumerate([few, base, few, base]):
         _say("replay", rep, b.name)
         tensors[0].copy_(torch.from_numpy(np.ascontiguousarray(b.vtx).view(np.int32)))
@@ -194,8 +201,9 @@ def test_batched_tuning_flags():
     b = meshgen.batched(300, 100, 5000, 0.05, 616)
     for fl in (mrx.MRX_TUNING_WIDE_LOOKBACK, mrx.MRX_TUNING_CLAIMED_TILES,
                mrx.MRX_TUNING_WIDE_LOOKBACK | mrx.MRX_TUNING_CLAIMED_TILES):
-        _say("batched flags", fl)
-        check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, fl)))
+        for strategy in (0, SORT_ALL):
+            _say("batched flags", fl | strategy)
+            check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, fl | strategy)))
 
 
 def test_batched_all_tunings_and_autotune(tmp_path):
@@ -204,8 +212,8 @@ def test_batched_all_tunings_and_autotune(tmp_path):
     b = meshgen.batched(50, 100, 6000, 0.05, 515)
     tensors = to_dev(b)
     for t in mrx.tunings(12):
-        _say("batched tuning", t.as_tuple())
-        check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=t))
+        _say("batched tuning", t.as_tuple(), "sort all")
+        check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=(*t.as_tuple(), SORT_ALL)))
     t, report = autotune.autotune(tensors[0], tensors[2], tensors[1], tensors[3], reps=2,
                                   path=str(tmp_path / "t.json"))
     check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=t))
@@ -215,14 +223,21 @@ def test_cfg4_full_batch():
     """The full 4096-mesh batch (~328M vertices) in one launch sequence:
     every mesh's output count matches its closed form, and every mesh
     matches the per-mesh oracle bit for bit (oracle calls spread over host
-    threads; each call releases the interpreter lock)."""
+    threads; each call releases the interpreter lock). The default (hash
+    grouping) is compared with the oracle, the sort-all path with it."""
     import concurrent.futures as cf
     import os
     import paper_2109_09812_amd as mrx
     _say("batch4096: generate")
     b = meshgen.cfg4()
     _say("batch4096: re-index", b.vtx.shape[0], "vertices")
-    res = mrx.reindex_mesh_batched(*to_dev(b))
+    tensors = to_dev(b)
+    res = mrx.reindex_mesh_batched(*tensors)
+    _say("batch4096: re-index, sort all")
+    other = mrx.reindex_mesh_batched(*tensors, tuning=(0, 0, 0, SORT_ALL))
+    for name in ("out_vtx_offsets", "out_vtx", "out_idx", "old2new", "new2old"):
+        assert torch.equal(getattr(res, name), getattr(other, name)), name
+    del other, tensors
     offs = res.out_vtx_offsets.cpu().numpy()
     assert np.array_equal(np.diff(offs), b.expected_unique)
     ov_all = res.out_vtx.cpu().numpy().view(np.uint32)
