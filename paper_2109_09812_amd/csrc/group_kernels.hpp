@@ -145,6 +145,18 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
   // built, the record's hash in `slot`; everything else lives in LDS, so
   // that three workgroups fit on a CU.
   uint32_t ids[IPT], slot[IPT];
+  // batches: mesh b's elements sit at sorted positions [mesh_off[b],
+  // mesh_off[b+1]) (its buckets follow those of the meshes before it), so a
+  // window inside one mesh needs one lookup, and otherwise a position's mesh
+  // is looked up instead of its id's
+  uint32_t win_mesh[2] = {0u, 1u};
+  if constexpr (MESH) {
+    const int64_t p0 = max(c0 - 1, int64_t(0)), p1 = min(c0 - 1 + WIN, n) - 1;
+    if (p0 <= p1) {
+      win_mesh[0] = __builtin_amdgcn_readfirstlane(mesh_of(a.mesh_off, a.nmesh, p0, a.mesh_tab));
+      win_mesh[1] = __builtin_amdgcn_readfirstlane(mesh_of(a.mesh_off, a.nmesh, p1, a.mesh_tab));
+    }
+  }
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const int q = i * BLOCK + tid;
@@ -158,7 +170,9 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
     }
     uint32_t key[KW];
     if constexpr (MESH) {
-      key[0] = (pos >= 0 && pos < n) ? mesh_of(a.mesh_off, a.nmesh, int64_t(e[K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
+      key[0] = (pos < 0 || pos >= n)            ? 0u
+               : win_mesh[0] == win_mesh[1] ? win_mesh[0]
+                                            : mesh_of(a.mesh_off, a.nmesh, pos, a.mesh_tab);
 #pragma unroll
       for (int w = 0; w < K; ++w) key[w + 1] = e[w];
     } else {

@@ -267,14 +267,24 @@ __device__ __forceinline__ void hash_mesh_hist_block(const uint32_t* __restrict_
 #pragma unroll
   for (int p = 0; p < PH; ++p) { last[p] = 0; run[p] = 0; }
   for (int64_t c = hb; c < chunks; c += nb) {
-    for (int it = 0; it < GROUPS; ++it) {
-      const int64_t i = c * (BLOCK * GROUPS) + int64_t(it) * BLOCK + threadIdx.x;
-      if (i >= n) break;
-      uint32_t x[K];
+    // a chunk inside one mesh (the usual case) needs one mesh lookup
+    const int64_t c0 = c * (BLOCK * GROUPS);
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(mesh_of(off, nmesh, c0, tab));
+    const uint32_t m1 = __builtin_amdgcn_readfirstlane(mesh_of(off, nmesh, min(c0 + BLOCK * GROUPS, n) - 1, tab));
+    // every load first (positions past the end read the last record)
+    uint32_t x[GROUPS][K];
 #pragma unroll
-      for (int w = 0; w < K; ++w) x[w] = vtx[i * K + w];
-      const uint32_t m = mesh_of(off, nmesh, i, tab);
-      const uint32_t bucket[1] = {mesh_bucket(mb, m, hash_mesh_words<K>(m, x))};
+    for (int it = 0; it < GROUPS; ++it) {
+      const int64_t i = min(c0 + int64_t(it) * BLOCK + threadIdx.x, n - 1);
+#pragma unroll
+      for (int w = 0; w < K; ++w) x[it][w] = vtx[i * K + w];
+    }
+#pragma unroll
+    for (int it = 0; it < GROUPS; ++it) {
+      const int64_t i = c0 + int64_t(it) * BLOCK + threadIdx.x;
+      if (i >= n) break;
+      const uint32_t m = m0 == m1 ? m0 : mesh_of(off, nmesh, i, tab);
+      const uint32_t bucket[1] = {mesh_bucket(mb, m, hash_mesh_words<K>(m, x[it]))};
       hist_item<DG, D>(bucket, s_h, last, run);
     }
   }
@@ -500,6 +510,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
   }
 
   // ---- digits
+  // first mesh-hash pass: the meshes of the tile's first and last vertex
+  uint32_t tile_mesh[2] = {0u, 1u};
+  if constexpr (kFirst && kMeshHash) {
+    tile_mesh[0] = __builtin_amdgcn_readfirstlane(mesh_of(a.mesh_off, a.nmesh, tile_base, a.mesh_tab));
+    tile_mesh[1] = __builtin_amdgcn_readfirstlane(
+        mesh_of(a.mesh_off, a.nmesh, tile_base + valid_count - 1, a.mesh_tab));
+  }
   uint32_t dig[IPT];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
@@ -510,7 +527,11 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(SortPassArgs a) {
     } else {
       if constexpr (kMeshHash) {
         const int64_t pos = wave_base + j * kWave;
-        const uint32_t m = pos < n ? mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab) : 0u;
+        uint32_t m = 0;
+        if (kFirst && tile_mesh[0] == tile_mesh[1])
+          m = tile_mesh[0];  // ids are positions; the whole tile is one mesh's
+        else if (pos < n)
+          m = mesh_of(a.mesh_off, a.nmesh, int64_t(v[j][K] & 0x7FFFFFFFu), a.mesh_tab);
         dig[j] = (mesh_bucket(a.mesh_buckets, m, hash_mesh_words<K>(m, v[j])) >> a.shift) & MASK;
       } else if constexpr (kHash)
         dig[j] = (hash_words<K>(v[j]) >> a.shift) & MASK;
