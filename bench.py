@@ -408,8 +408,24 @@ def bench_batched(args, torch, mrx, meshgen):
             "per_mesh_tunings": {k.split("|")[2]: list(t.as_key()) for k, t in sorted(bucket_tuning.items())},
             "batched_vertices_per_s": n / (ms_b * 1e-3), "per_mesh_vertices_per_s": n / (ms_p * 1e-3),
             "speedup": round(ms_p / ms_b, 2), "batched_equals_per_mesh": bool(same),
-            "tuning": list(t.as_key()),
+            "tuning": list(t.as_key()), "strategy": strategy_name(t.as_key()[3]),
+            "autotune_best_ms_by_strategy": best_by_strategy(report),
             "closed_form_counts_ok": exp_ok, "merge": merge}
+
+
+def strategy_name(flags):
+    return "hash grouping" if flags & 8 else "sort all" if flags & 4 else "library default"
+
+
+def best_by_strategy(report):
+    """Fastest autotuner time of each strategy (None if the tuner's cache answered)."""
+    out = {}
+    for key, ms in report.items():
+        if not isinstance(key, tuple) or len(key) != 4:
+            return None
+        name = strategy_name(key[3])
+        out[name] = round(min(ms, out.get(name, float("inf"))), 3)
+    return out
 
 
 def _sampled_records_ok(vtx_np, src_rows, out_idx, out_vtx, new2old, rng, count=20000):
@@ -648,8 +664,15 @@ def batched_kernels_only(args, torch, mrx, meshgen):
     for _ in range(args.warmup + args.steps):
         r.launch()
     torch.cuda.synchronize()
+    # the same 1 GiB copy probe as kernels_only, to calibrate the counters
+    a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(7)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
     print(json.dumps({"mode": "batched-kernels", "steps": args.steps, "warmup": args.warmup,
-                      "tuning": list(tuning), "total_vertices": int(b.vtx.shape[0])}))
+                      "tuning": list(tuning), "total_vertices": int(b.vtx.shape[0]),
+                      "copy_probe_bytes_each_way": a.numel() * 4}))
 
 
 def main():
