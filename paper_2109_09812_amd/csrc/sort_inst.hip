@@ -335,6 +335,12 @@ SortVariant make() {
 
 void MRX_CAT(register_k, MRX_INST_K)(std::vector<SortVariant>& out) {
   out.push_back(make<8, 256, default_ipt(K)>());  // variant 0: default
+#if MRX_INST_K != 2 && MRX_INST_K != 3 && MRX_INST_K != 8
+  // every other width: larger tiles with half the items per thread, and
+  // smaller workgroups
+  out.push_back(make<8, 512, (default_ipt(K) / 2 > 2 ? default_ipt(K) / 2 : 2)>());
+  out.push_back(make<8, 128, default_ipt(K)>());
+#endif
 #if MRX_INST_K == 2 || MRX_INST_K == 3
   out.push_back(make<8, 512, 16>());
   out.push_back(make<8, 256, 12>());

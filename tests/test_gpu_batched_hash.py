@@ -73,14 +73,16 @@ def test_batched_hash_lookback_flags(fl):
     check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH | fl)))
 
 
-@pytest.mark.parametrize("words", [1, 2, 4, 5, 8, 15, 16])
+@pytest.mark.parametrize("words", [1, 2, 3, 4, 5, 6, 7, 8, 11, 15, 16])
 def test_batched_hash_record_widths(words):
-    """Every record width, 1 to 16 words."""
+    """Every record width, 1 to 16 words, every compiled variant."""
     import paper_2109_09812_amd as mrx
     sizes = [5000, 1, 0, 23_001, 777, 9000, 40_000, 2]
     b = pooled_batch(sizes, words, 70 + words)
-    _say("hash batch width", words, b.vtx.shape[0], "vertices")
-    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, HASH)))
+    tensors = to_dev(b)
+    for t in mrx.tunings(4 * words):
+        _say("hash batch width", words, b.vtx.shape[0], "vertices", t.as_tuple())
+        check_batch(b, mrx.reindex_mesh_batched(*tensors, tuning=(*t.as_tuple(), HASH)))
 
 
 def test_batched_hash_every_tuning():

@@ -163,15 +163,16 @@ def test_wide_records_all_tunings():
 
 def test_every_record_width_every_tuning():
     """Records of 1-16 words, every compiled variant of each width, on meshes
-    of several tiles with a ragged tail. Narrow records (up to 4 words) run the
-    used marking and digit histograms as one launch, wider ones as two; the
-    lopsided shapes give that launch almost only histogram tiles, or almost
-    only marking tiles."""
+    of several tiles with a ragged tail, sorting all and with hash grouping.
+    Narrow records (up to 4 words) run the used marking and digit histograms
+    as one launch, wider ones as two; the lopsided shapes give that launch
+    almost only histogram tiles, or almost only marking tiles."""
     import paper_2109_09812_amd as mrx
     for k in range(1, 17):
         vtx, idx = meshgen.random_mesh(20_011 + 97 * k, 7_001, 3, k, 2_500, 4_700 + k, 0.9)
         for t in mrx.tunings(4 * k):
-            assert_parity(vtx, idx, tuning=t, name=f"width {k}")
+            for strategy in (mrx.MRX_TUNING_SORT_ALL, mrx.MRX_TUNING_HASH_GROUPS):
+                assert_parity(vtx, idx, tuning=(*t.as_tuple(), strategy), name=f"width {k}")
     for k in (2, 3, 5):
         assert_parity(*meshgen.random_mesh(300_007, 1, 3, k, 40_000, 4_800 + k), name=f"one element {k}")
         assert_parity(*meshgen.random_mesh(37, 200_003, 3, k, 20, 4_900 + k), name=f"many elements {k}")
