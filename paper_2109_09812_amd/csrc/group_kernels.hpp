@@ -18,9 +18,14 @@
 // chunk's, and its k-th group (in order of first copy) is called span start +
 // k, its k-th used group's element goes to slot span start + k of the
 // element buffer. Names stay below N and need no count of earlier chunks, so
-// the chunks never wait for each other; k_group_scan then adds up the per-chunk
-// counts, and k_group_compact_hist packs the used groups' elements densely
-// while counting their key digits.
+// the chunks never wait for each other; the chunks' counts go to per-run
+// sums, and k_group_compact_hist adds those up and packs the used groups'
+// elements densely while counting their key digits.
+//
+// A batch groups by (mesh id, record): every mesh owns a range of buckets,
+// so its vertices end up at the sorted positions of its own vertex range,
+// and a group is named by the position of its first copy instead, which
+// lies in that range (the name tells the group's mesh).
 //
 // A bucket that does not fit the LDS window (many copies of one value, or an
 // unlucky hash) makes the call take the plain path instead: the same key
@@ -290,7 +295,7 @@ __global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
   }
 
   // ---- the chunk's record and its share of its run's sums; names start at
-  // the span's first position
+  // the span's first position (batches: the first copy's position)
   const uint32_t span0 = owns ? uint32_t(c0 - 1 + sq) : 0u;
   if (tid == 0) {
     const uint32_t u_own = active ? ut : 0u, g_own = active ? gt : 0u;
