@@ -115,9 +115,18 @@ __device__ __forceinline__ bool lds_keys_equal(const uint32_t* s_keys, int a, in
 // of sorted positions (its buckets come after those of the meshes before
 // it), and a group is named by the sorted position of its first copy, which
 // lies in that range: the mesh of a group is the mesh of its name.
+// Waves per SIMD the grouping kernel's registers are budgeted for: the
+// shape's, except for batches of 1- and 2-word records, whose mesh-id key
+// word and lookups would otherwise spill to scratch at that budget.
 template <int K, bool MESH>
-__global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK,
-                             GroupShape<MESH ? K + 1 : K>::MIN_WAVES_PER_SIMD) void k_group(GroupArgs a) {
+constexpr int group_min_waves() {
+  return MESH && K <= 2 ? GroupShape<K + 1>::MIN_WAVES_PER_SIMD - 1
+                        : GroupShape<MESH ? K + 1 : K>::MIN_WAVES_PER_SIMD;
+}
+
+template <int K, bool MESH>
+__global__ __launch_bounds__(GroupShape<MESH ? K + 1 : K>::BLOCK, (group_min_waves<K, MESH>())) void k_group(
+    GroupArgs a) {
   constexpr int KW = MESH ? K + 1 : K;  // key words
   using SH = GroupShape<KW>;
   constexpr int S = K + 1;              // words of an input element
