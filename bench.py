@@ -343,6 +343,38 @@ def bench_batched(args, torch, mrx, meshgen):
         ref_b += reference_model_bytes(nb, mb, ub + (nb - mb), ub, 12)[0]
     batched_pipeline = {"model": "Section 2 pipeline per mesh, 8-bit LSD digits over all key bits",
                         "model_bytes": int(ref_b), "frac": round(ref_b / (ms_b * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)}
+    # algorithmic bytes per launch of the kernels of the hash-grouping path
+    # (N vertices, M index entries, G distinct and U used values over all
+    # meshes; random 1-4 byte accesses counted at their size)
+    u_all = int(b.expected_unique.sum())
+    g_all = int(u_all + (sizes_v - sizes_i).sum())
+    m_all = int(sizes_i.sum())
+    s_el = 16
+    bmodel = {
+        "mark_histogram": 5 * m_all + 12 * n,
+        "onesweep_hash_first": 12 * n + n + n * s_el,
+        "onesweep_hash": 2 * n * s_el,
+        "group": n * s_el + 8 * n + 4 * g_all + 4 * (g_all - u_all) + u_all * s_el,
+        "compact_histogram": 2 * u_all * s_el,
+        "onesweep": 2 * u_all * s_el,
+        "onesweep_mesh": 2 * u_all * s_el,
+        "finalize": u_all * s_el + 12 * u_all + 12 * u_all,
+        "old2new": 12 * n + 4 * g_all,
+        "localize_new2old": 8 * u_all,
+        "remap": 12 * m_all,
+    } if "group" in btable else {}
+    if bmodel and t.as_key()[0] in (0, 8):
+        # key passes whose digit is the same for every used value move
+        # nothing (read off the output records; 8-bit digits)
+        ow = res.out_vtx[:u_all].cpu().numpy().view("uint32").reshape(u_all, 3)
+        dead = sum(1 for p in range(12)
+                   if u_all == 0 or np.all(((ow[:, 2 - p // 4] >> np.uint32(8 * (p % 4))) & np.uint32(255)) ==
+                                           ((ow[0, 2 - p // 4] >> np.uint32(8 * (p % 4))) & np.uint32(255))))
+        bmodel["onesweep"] = bmodel["onesweep"] * (12 - dead) // 12   # average over the launches
+    for name, nbytes in bmodel.items():
+        if name in bkernels and btable[name][1] > 0:
+            bkernels[name]["model_bytes"] = nbytes
+            bkernels[name]["model_GBps"] = round(nbytes / (btable[name][1] * 1e-3) / 1e9, 1)
 
     # per-mesh launches: one mrx_reindex_mesh per mesh on one stream, shared
     # workspace, outputs at the mesh's own offsets, no synchronisation; each
