@@ -171,6 +171,12 @@ def test_tuning_flags():
     assert _ws(60_000, 12, 50_000, 2) == _ws(60_000, 12, 50_000, 2, tuning=(0, 0, 0, sort_all))
     assert (_ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, hashed))[1] >
             _ws(100_000, 64, 90_000, 2, tuning=(0, 0, 0, sort_all))[1])
+    # a batch needing more than 2^24 hash buckets (at least one per mesh)
+    # sorts all whatever the flags say
+    many = (1 << 26, 12, 1 << 25, 20_000_000)
+    assert _ws(*many, tuning=(0, 0, 0, hashed)) == _ws(*many, tuning=(0, 0, 0, sort_all))
+    few = (1 << 26, 12, 1 << 25, 1_000_000)
+    assert _ws(*few, tuning=(0, 0, 0, hashed))[1] > _ws(*few, tuning=(0, 0, 0, sort_all))[1]
 
 
 def test_workspace_one_byte_short():
