@@ -184,3 +184,26 @@ def test_batched_hash_graph_switches_paths():
         torch.cuda.synchronize()
         check_batch(b, gr.result())
         _ = (tensors[0].float() * 2).sum().item()
+
+
+def test_batched_hash_no_elements_and_all_distinct():
+    """Vertices but no index entries at all (every value unused, U = 0), and
+    every vertex distinct and referenced (U = N)."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(12)
+    sizes = [40_000, 0, 30_001, 7]
+    n = sum(sizes)
+    vo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    vtx = rng.integers(0, 2**32, size=(n, 3), dtype=np.uint64).astype(np.uint32)
+    none = meshgen.Batch(vtx, np.zeros((0, 3), np.int32), vo, np.zeros(5, np.int64), None, "no elements")
+    _say("hash batch without elements", n, "vertices")
+    check_batch(none, mrx.reindex_mesh_batched(*to_dev(none), tuning=(0, 0, 0, HASH)))
+    # every vertex of every mesh referenced once, all values distinct
+    parts, eo = [], [0]
+    for sz in sizes:
+        perm = rng.permutation(sz - sz % 3).astype(np.int32).reshape(-1, 3)
+        parts.append(perm)
+        eo.append(eo[-1] + perm.shape[0])
+    dense = meshgen.Batch(vtx, np.concatenate(parts), vo, np.array(eo, np.int64), None, "all distinct")
+    _say("hash batch, all distinct and used")
+    check_batch(dense, mrx.reindex_mesh_batched(*to_dev(dense), tuning=(0, 0, 0, HASH)))
