@@ -173,7 +173,7 @@ def choose_tuning(args, vtx, idx):
     tuning = args.tuning
     if tuning is None:
         from paper_2109_09812_amd import autotune
-        t, report = autotune.autotune(vtx, idx, reps=3)
+        t, report = autotune.autotune(vtx, idx, reps=10)
         tuning = t.as_key()
         log(f"autotuned: {tuning} from {report}")
     args.chosen_tuning = tuning
@@ -313,7 +313,7 @@ def bench_batched(args, torch, mrx, meshgen):
     idx = torch.from_numpy(b.idx).to(dev)
     eo = torch.from_numpy(b.elem_offsets).to(dev)
     from paper_2109_09812_amd import autotune
-    t, report = autotune.autotune(vtx, idx, vo, eo, reps=2)
+    t, report = autotune.autotune(vtx, idx, vo, eo, reps=4)
     log(f"batch4096: N={n} meshes={b.num_meshes}; autotuned {t.as_key()} from {report}; capturing graph")
     g = mrx.GraphedBatchedReindexer(vtx, vo, idx, eo, tuning=t)
     g.replay()
