@@ -207,3 +207,24 @@ def test_batched_hash_no_elements_and_all_distinct():
     dense = meshgen.Batch(vtx, np.concatenate(parts), vo, np.array(eo, np.int64), None, "all distinct")
     _say("hash batch, all distinct and used")
     check_batch(dense, mrx.reindex_mesh_batched(*to_dev(dense), tuning=(0, 0, 0, HASH)))
+
+
+@pytest.mark.parametrize("strategy", [HASH, 4])
+def test_batched_many_tiny_meshes(strategy):
+    """70,000 meshes of 0-9 vertices: three mesh-id digits, a bucket table
+    built over many workgroup-sized rounds, one bucket per mesh."""
+    import paper_2109_09812_amd as mrx
+    rng = np.random.default_rng(70_000)
+    sizes = rng.integers(0, 10, 70_000)
+    n = int(sizes.sum())
+    vo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pool = rng.integers(0, 2**32, size=(50, 2), dtype=np.uint64).astype(np.uint32)
+    vtx = pool[rng.integers(0, 50, n)]
+    parts, eo = [], [0]
+    for sz in sizes.tolist():
+        e = int(rng.integers(0, 4)) if sz else 0
+        parts.append(rng.integers(0, max(sz, 1), size=(e, 2)).astype(np.int32))
+        eo.append(eo[-1] + e)
+    b = meshgen.Batch(vtx, np.concatenate(parts), vo, np.array(eo, np.int64), None, "tiny meshes")
+    _say("batch of", len(sizes), "tiny meshes,", n, "vertices, strategy", strategy)
+    check_batch(b, mrx.reindex_mesh_batched(*to_dev(b), tuning=(0, 0, 0, strategy)))
