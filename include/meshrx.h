@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MRX_ABI_VERSION 5
+#define MRX_ABI_VERSION 6
 
 typedef enum {
   MRX_OK = 0,

@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     lib = _lib.load()
-    assert lib.mrx_abi_version() == 5
+    assert lib.mrx_abi_version() == 6
     for code, name in [(0, "MRX_OK"), (1, "MRX_ERR_INVALID_ARGUMENT"), (2, "MRX_ERR_WORKSPACE_TOO_SMALL"),
                        (3, "MRX_ERR_INDEX_OUT_OF_RANGE"), (4, "MRX_ERR_TOO_LARGE"), (5, "MRX_ERR_HIP"),
                        (6, "MRX_ERR_UNSUPPORTED"), (7, "MRX_ERR_INTERNAL")]:
